@@ -1,0 +1,99 @@
+// mce_internal.h -- types shared by the device kernels and the host runtime of
+// libmce.so.  Not part of the public ABI (include/mce.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mce {
+
+constexpr uint32_t kMaxN = 4096;
+// Per-wavefront clique buffer in LDS: sorted input ids (u16) of cliques waiting
+// to be hashed, and one entry word (start | size << 16) per clique.
+constexpr uint32_t kCliqueIds = 1024;
+constexpr uint32_t kCliqueEntries = 64;
+// Per-wavefront LDS histogram; larger clique sizes go straight to HBM.
+constexpr uint32_t kHistLds = 64;
+// Words at the head of a queue record (graph index, spare).
+constexpr uint32_t kRecHeader = 2;
+// LDS words of a wavefront before its stack window:
+// hist (kHistLds u64) + entries (kCliqueEntries u32) + ids (kCliqueIds u16).
+constexpr uint32_t kWaveFixedWords = kHistLds * 2 + kCliqueEntries + kCliqueIds / 2;
+
+// One graph of a handle, in device memory.
+struct GraphDesc {
+    uint32_t n;        // vertices
+    uint32_t w32;      // 32-bit words of a bitset, ceil(n/32)
+    uint32_t rw64;     // uint64 words of an input row, ceil(n/64)
+    uint32_t pad;
+    uint64_t in_off;   // first uint64 word of the input rows
+    uint64_t adj_off;  // first uint32 word of the renumbered rows (row stride w32)
+    uint64_t ord_off;  // first entry of order[] (position -> input id)
+    uint64_t hist_off; // first entry of the graph's histogram (n + 1 entries)
+};
+
+// Per-graph totals, accumulated with device atomics.
+struct DevResult {
+    unsigned long long count, nodes, children, dead_ends, hash_xor, hash_sum;
+    unsigned long long root_branches;
+    unsigned int omega, status;
+};
+
+// Control block of one search launch.
+struct QueueCtl {
+    unsigned int head, tail, pending, error;
+    unsigned long long donations, units;
+    unsigned long long spill_next;           // next free chunk of the spill pool
+    unsigned long long spill_levels_written; // stack levels stored in HBM
+    unsigned long long vcursor, ocursor;     // enumerate output cursors
+};
+// QueueCtl.error bits
+constexpr unsigned int kErrSpill = 1u; // spill pool exhausted: rerun with a larger pool
+constexpr unsigned int kErrDepth = 2u; // stack deeper than a spill chunk (a bug)
+constexpr unsigned int kErrWatchdog = 4u; // the search ran past its deadline
+
+struct SearchParams {
+    const GraphDesc* graphs;
+    const uint32_t* adj;
+    const uint32_t* order;
+    DevResult* results;
+    unsigned long long* hist;
+    QueueCtl* ctl;
+    unsigned int* seq;        // queue sequence numbers, cap entries
+    uint32_t* rec;            // queue records, cap * rec_words
+    uint32_t* spill;          // per wavefront: spill_levels * slot_words
+    uint32_t* verts;          // enumerate output (device) or nullptr
+    unsigned long long* offs;
+    unsigned long long verts_cap, offs_cap;
+    uint32_t cap_mask;
+    uint32_t rec_words;       // kRecHeader + 4 * w32cap
+    uint32_t w32cap;          // bitset stride in LDS slots and records
+    uint32_t slot_words;      // 3 * w32cap + 1
+    uint32_t lds_depth;       // stack levels in LDS
+    uint32_t spill_levels;    // stack levels in one spill chunk
+    uint32_t spill_chunks;    // chunks in the spill pool
+    uint32_t wave_lds_words;  // LDS words per wavefront
+    uint32_t split_threshold;
+    uint32_t check_interval;
+    uint32_t enumerate;
+    uint64_t watchdog_ticks;  // wall-clock ticks a wavefront may run (0 = no limit)
+};
+
+// Host-side launchers (kernels.hip).
+hipError_t launch_validate(const uint64_t* rows, uint32_t n, uint32_t rw, unsigned int* flag,
+                           hipStream_t s);
+hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
+                        const uint64_t* rows_in, uint32_t* order, hipStream_t s);
+hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
+                          const uint64_t* rows_in, const uint32_t* order, uint32_t* adj,
+                          hipStream_t s);
+hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
+                        uint32_t cap, hipStream_t s);
+hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
+                       uint64_t first, uint64_t last, hipStream_t s);
+hipError_t launch_search(const SearchParams& sp, uint32_t max_w32, uint32_t blocks,
+                         uint32_t waves_per_block, hipStream_t s);
+hipError_t search_occupancy(uint32_t max_w32, uint32_t waves_per_block, uint32_t lds_bytes,
+                            int* blocks_per_cu);
+
+} // namespace mce

@@ -1,0 +1,1097 @@
+// runtime.hip -- host side of libmce.so: the C ABI of include/mce.h.
+//
+// Responsibilities: input validation (before any HIP call), device buffers of
+// a handle, launch configuration of the persistent search, result copy-out,
+// the per-handle hipGraph of the solve sequence, and the serving scheduler.
+#include "mce.h"
+#include "mce_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+using namespace mce;
+
+namespace {
+
+// ------------------------------------------------------------ options ----
+
+struct Options {
+    int64_t waves_per_block = 0; // 0: auto
+    int64_t blocks = 0;          // 0: fill the device
+    int64_t lds_depth = -1;      // -1: auto
+    int64_t split_threshold = 0; // 0: auto
+    int64_t check_interval = 0;  // 0: auto
+    int64_t queue_cap = 0;       // 0: auto
+    int64_t watchdog_ms = 0;     // 0: none
+    int64_t graph = 1;           // hipGraph replay: 0 never, 1 batches, 2 always
+};
+
+std::mutex g_opt_mu;
+Options g_opt;
+
+Options options()
+{
+    std::lock_guard<std::mutex> lk(g_opt_mu);
+    return g_opt;
+}
+
+thread_local mce_stats_t t_stats;
+
+// ------------------------------------------------------------- device ----
+
+struct DeviceInfo {
+    int ok = 0;
+    int device = -1;
+    int cus = 0;
+    size_t lds_per_block = 0;
+    int wall_khz = 0;
+};
+
+std::mutex g_dev_mu;
+DeviceInfo g_dev;
+bool g_dev_probed = false;
+
+// The library runs on the current HIP device, which must be a gfx950.
+int device_info(DeviceInfo* out)
+{
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return MCE_E_DEVICE;
+    if (!g_dev_probed || g_dev.device != dev) {
+        g_dev_probed = true;
+        g_dev = DeviceInfo();
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MCE_E_DEVICE;
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MCE_E_DEVICE;
+        g_dev.device = dev;
+        g_dev.cus = prop.multiProcessorCount;
+        g_dev.lds_per_block = prop.sharedMemPerBlock;
+        if (hipDeviceGetAttribute(&g_dev.wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+            g_dev.wall_khz = 0;
+        g_dev.ok = 1;
+    }
+    if (!g_dev.ok) return MCE_E_DEVICE;
+    *out = g_dev;
+    return MCE_OK;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return hip_status(_e);    \
+    } while (0)
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return MCE_OK;
+    if (e == hipErrorOutOfMemory) return MCE_E_NOMEM;
+    return MCE_E_DEVICE;
+}
+
+// Caching device allocator: freed blocks stay with the library and are handed
+// out again, so handles created per request do not pay for hipMalloc.  Sizes
+// are rounded up to a power of two (at least 4 KiB).  Blocks are returned only
+// when the device has finished with them (callers synchronise first).
+struct Pool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free_blocks;
+    size_t cached = 0;
+};
+
+Pool& pool()
+{
+    static Pool* p = new Pool(); // never destroyed: HIP may be torn down first at exit
+    return *p;
+}
+
+size_t pool_round(size_t want)
+{
+    size_t r = 4096;
+    while (r < want) r <<= 1;
+    return r;
+}
+
+void* pool_alloc(size_t want, size_t* got)
+{
+    const size_t sz = pool_round(want);
+    Pool& pl = pool();
+    {
+        std::lock_guard<std::mutex> lk(pl.mu);
+        auto it = pl.free_blocks.find(sz);
+        if (it != pl.free_blocks.end()) {
+            void* p = it->second;
+            pl.free_blocks.erase(it);
+            pl.cached -= sz;
+            *got = sz;
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        // give the cached blocks back to HIP and retry once
+        std::lock_guard<std::mutex> lk(pl.mu);
+        for (auto& kv : pl.free_blocks) (void)hipFree(kv.second);
+        pl.free_blocks.clear();
+        pl.cached = 0;
+        if (hipMalloc(&p, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    *got = sz;
+    return p;
+}
+
+void pool_free(void* p, size_t sz)
+{
+    if (!p) return;
+    Pool& pl = pool();
+    std::lock_guard<std::mutex> lk(pl.mu);
+    pl.free_blocks.emplace(sz, p);
+    pl.cached += sz;
+}
+
+// Grow-only device buffer on the caching allocator.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    void reset()
+    {
+        pool_free(p, bytes);
+        p = nullptr;
+        bytes = 0;
+    }
+    int ensure(size_t want)
+    {
+        if (want <= bytes && p) return MCE_OK;
+        reset();
+        p = pool_alloc(want ? want : 8, &bytes);
+        if (!p) {
+            bytes = 0;
+            return MCE_E_NOMEM;
+        }
+        return MCE_OK;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct HostPinned {
+    void* p = nullptr;
+    size_t bytes = 0;
+    HostPinned() = default;
+    HostPinned(const HostPinned&) = delete;
+    HostPinned& operator=(const HostPinned&) = delete;
+    ~HostPinned() { reset(); }
+    void reset()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int ensure(size_t want)
+    {
+        if (want <= bytes && p) return MCE_OK;
+        reset();
+        if (want == 0) want = 8;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return MCE_E_NOMEM;
+        }
+        bytes = want;
+        return MCE_OK;
+    }
+};
+
+uint32_t next_pow2(uint64_t x)
+{
+    uint32_t r = 1;
+    while (r < x && r < (1u << 30)) r <<= 1;
+    return r;
+}
+
+// ----------------------------------------------------------- validation --
+
+// A simple graph: zero diagonal, no bit at a column >= n, symmetric.
+int validate_host(uint32_t n, const uint64_t* rows, uint64_t rs)
+{
+    if (n > MCE_MAX_N) return MCE_E_INVAL;
+    if (n == 0) return MCE_OK;
+    if (!rows) return MCE_E_INVAL;
+    if (rs * 64u < n) return MCE_E_INVAL;
+    for (uint32_t i = 0; i < n; i++) {
+        const uint64_t* r = rows + (uint64_t)i * rs;
+        for (uint64_t w = 0; w < rs; w++) {
+            uint64_t x = r[w];
+            const uint64_t lo = w * 64u;
+            if (lo + 64u > n) {
+                const uint64_t valid = (lo >= n) ? 0ull : ((1ull << (n - lo)) - 1ull);
+                if (x & ~valid) return MCE_E_INVAL;
+            }
+            while (x) {
+                const uint32_t b = (uint32_t)__builtin_ctzll(x);
+                x &= x - 1;
+                const uint32_t j = (uint32_t)(lo + b);
+                if (j == i) return MCE_E_INVAL;
+                if (!((rows[(uint64_t)j * rs + (i >> 6)] >> (i & 63)) & 1u)) return MCE_E_INVAL;
+            }
+        }
+    }
+    return MCE_OK;
+}
+
+// ------------------------------------------------------ launch config ----
+
+struct LaunchCfg {
+    uint32_t wpb = 4;
+    uint32_t blocks = 0;
+    uint32_t lds_depth = 16;
+    uint32_t split_threshold = 0;
+    uint32_t check_interval = 32;
+    uint32_t cap = 0;
+    uint32_t wave_lds_words = 0;
+    uint32_t slot_words = 0;
+    uint32_t w32cap = 0;
+    uint32_t spill_levels = 0;
+    uint32_t spill_chunks = 0;
+    bool operator==(const LaunchCfg& o) const
+    {
+        return wpb == o.wpb && blocks == o.blocks && lds_depth == o.lds_depth &&
+               split_threshold == o.split_threshold && check_interval == o.check_interval &&
+               cap == o.cap && wave_lds_words == o.wave_lds_words && slot_words == o.slot_words &&
+               w32cap == o.w32cap && spill_levels == o.spill_levels && spill_chunks == o.spill_chunks;
+    }
+};
+
+} // namespace
+
+// ------------------------------------------------------------- handle ----
+
+struct mce_graph_s {
+    std::mutex mu;
+    int device = -1;
+    uint32_t num_graphs = 0;
+    std::vector<GraphDesc> desc;
+    uint32_t max_n = 0, max_w32 = 0;
+    uint64_t in_words = 0, adj_words = 0, ord_words = 0, hist_total = 0;
+    DevBuf d_desc, d_in, d_adj, d_order;
+    // workspace of the solve
+    DevBuf d_results, d_hist, d_ctl, d_seq, d_rec, d_spill;
+    HostPinned h_out; // results | ctl | hist, copied back in one go
+    LaunchCfg cfg;
+    bool cfg_valid = false;
+    hipGraphExec_t graph_exec = nullptr;
+    LaunchCfg graph_cfg;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    float prepare_ms = 0.f;
+    bool prepared_timed = false;
+    ~mce_graph_s()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+size_t out_bytes(const mce_graph_s* h)
+{
+    return sizeof(DevResult) * h->num_graphs + sizeof(QueueCtl) + 8 * h->hist_total;
+}
+
+int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32_t blocks_cap = 0)
+{
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc != MCE_OK) return rc;
+    const Options o = options();
+    LaunchCfg c;
+    c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16) : 4u;
+    c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
+    c.slot_words = 3 * c.w32cap + 1;
+    uint32_t depth = o.lds_depth >= 0 ? (uint32_t)std::min<int64_t>(o.lds_depth, 64) : 16u;
+    // keep a workgroup within the LDS limit
+    for (;;) {
+        uint32_t wl = kWaveFixedWords + depth * c.slot_words;
+        wl = (wl + 1u) & ~1u;
+        if ((size_t)wl * 4u * c.wpb <= di.lds_per_block || (depth == 0 && c.wpb == 1)) {
+            c.wave_lds_words = wl;
+            break;
+        }
+        if (depth > 0) depth--;
+        else c.wpb--;
+    }
+    c.lds_depth = depth;
+    const uint32_t lds_bytes = c.wave_lds_words * 4u * c.wpb;
+    if (o.blocks > 0) {
+        c.blocks = (uint32_t)o.blocks;
+    } else {
+        int bpc = 0;
+        HIP_TRY(search_occupancy(h->max_w32, c.wpb, lds_bytes, &bpc));
+        if (bpc < 1) bpc = 1;
+        c.blocks = (uint32_t)di.cus * (uint32_t)bpc;
+    }
+    if (blocks_cap && c.blocks > blocks_cap) c.blocks = blocks_cap;
+    const uint32_t waves = c.blocks * c.wpb;
+    c.split_threshold = o.split_threshold > 0 ? (uint32_t)o.split_threshold : std::max<uint32_t>(waves / 8u, 4u);
+    c.check_interval = o.check_interval > 0 ? (uint32_t)o.check_interval : 32u;
+    uint64_t cap = o.queue_cap > 0 ? (uint64_t)o.queue_cap
+                                   : std::max<uint64_t>({(uint64_t)waves * 2u, (uint64_t)h->num_graphs * 2u, 1024u});
+    cap = std::max<uint64_t>(cap, (uint64_t)h->num_graphs + 1u);
+    c.cap = next_pow2(cap);
+    c.spill_levels = h->max_n > c.lds_depth ? h->max_n - c.lds_depth : 1u;
+    c.spill_chunks = std::max<uint32_t>(std::min<uint32_t>(waves, 64u), spill_chunks_floor);
+    c.spill_chunks = std::min<uint32_t>(c.spill_chunks, waves);
+    *cfg = c;
+    return MCE_OK;
+}
+
+int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
+{
+    int rc;
+    if ((rc = h->d_results.ensure(sizeof(DevResult) * h->num_graphs)) != MCE_OK) return rc;
+    if ((rc = h->d_hist.ensure(8 * std::max<uint64_t>(h->hist_total, 1))) != MCE_OK) return rc;
+    if ((rc = h->d_ctl.ensure(sizeof(QueueCtl))) != MCE_OK) return rc;
+    if ((rc = h->d_seq.ensure(4ull * c.cap)) != MCE_OK) return rc;
+    const uint64_t rec_words = kRecHeader + 4ull * c.w32cap;
+    if ((rc = h->d_rec.ensure(4ull * rec_words * c.cap)) != MCE_OK) return rc;
+    const uint64_t spill = 4ull * c.slot_words * c.spill_levels * c.spill_chunks;
+    if ((rc = h->d_spill.ensure(spill)) != MCE_OK) return rc;
+    if ((rc = h->h_out.ensure(out_bytes(h))) != MCE_OK) return rc;
+    return MCE_OK;
+}
+
+SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
+{
+    SearchParams sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.graphs = h->d_desc.as<GraphDesc>();
+    sp.adj = h->d_adj.as<uint32_t>();
+    sp.order = h->d_order.as<uint32_t>();
+    sp.results = h->d_results.as<DevResult>();
+    sp.hist = h->d_hist.as<unsigned long long>();
+    sp.ctl = h->d_ctl.as<QueueCtl>();
+    sp.seq = h->d_seq.as<unsigned int>();
+    sp.rec = h->d_rec.as<uint32_t>();
+    sp.spill = h->d_spill.as<uint32_t>();
+    sp.cap_mask = c.cap - 1;
+    sp.rec_words = kRecHeader + 4 * c.w32cap;
+    sp.w32cap = c.w32cap;
+    sp.slot_words = c.slot_words;
+    sp.lds_depth = c.lds_depth;
+    sp.spill_levels = c.spill_levels;
+    sp.spill_chunks = c.spill_chunks;
+    sp.wave_lds_words = c.wave_lds_words;
+    sp.split_threshold = c.split_threshold;
+    sp.check_interval = c.check_interval;
+    const Options o = options();
+    DeviceInfo di;
+    if (o.watchdog_ms > 0 && device_info(&di) == MCE_OK && di.wall_khz > 0)
+        sp.watchdog_ticks = (uint64_t)o.watchdog_ms * (uint64_t)di.wall_khz;
+    return sp;
+}
+
+// The solve sequence on a stream: reset, root, search, copy-out.
+int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, uint64_t first,
+                  uint64_t last, hipStream_t s, bool timed)
+{
+    HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.cap, s));
+    HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, s));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
+    HIP_TRY(launch_search(sp, h->max_w32, c.blocks, c.wpb, s));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
+    char* out = static_cast<char*>(h->h_out.p);
+    HIP_TRY(hipMemcpyAsync(out, sp.results, sizeof(DevResult) * h->num_graphs, hipMemcpyDeviceToHost, s));
+    out += sizeof(DevResult) * h->num_graphs;
+    HIP_TRY(hipMemcpyAsync(out, sp.ctl, sizeof(QueueCtl), hipMemcpyDeviceToHost, s));
+    out += sizeof(QueueCtl);
+    if (h->hist_total)
+        HIP_TRY(hipMemcpyAsync(out, sp.hist, 8 * h->hist_total, hipMemcpyDeviceToHost, s));
+    return MCE_OK;
+}
+
+void fill_result(const mce_graph_s* h, uint32_t gi, const DevResult& r, const uint64_t* hist,
+                 mce_result_t* out)
+{
+    const GraphDesc& gd = h->desc[gi];
+    out->count = r.count;
+    out->nodes = r.nodes;
+    out->children = r.children;
+    out->dead_ends = r.dead_ends;
+    out->hash_xor = r.hash_xor;
+    out->hash_sum = r.hash_sum;
+    out->omega = r.omega;
+    out->status = MCE_OK;
+    if (out->hist && out->hist_len) {
+        const uint32_t len = out->hist_len;
+        for (uint32_t k = 0; k < len; k++) out->hist[k] = (k <= gd.n) ? hist[gd.hist_off + k] : 0ull;
+    }
+}
+
+// n = 0: the empty clique only.
+void fill_empty_graph(uint64_t first, uint64_t last, mce_result_t* out)
+{
+    const bool root = first == 0 && last > 0;
+    out->count = root ? 1 : 0;
+    out->nodes = out->children = out->dead_ends = 0;
+    out->hash_xor = out->hash_sum = 0; // h({}) = mix64(0) = 0
+    out->omega = 0;
+    out->status = MCE_OK;
+    if (out->hist && out->hist_len) {
+        std::memset(out->hist, 0, 8ull * out->hist_len);
+        out->hist[0] = root ? 1 : 0;
+    }
+}
+
+int read_results(mce_graph_s* h, uint64_t first, uint64_t last, mce_result_t* res, QueueCtl* ctl_out)
+{
+    const char* out = static_cast<const char*>(h->h_out.p);
+    const DevResult* r = reinterpret_cast<const DevResult*>(out);
+    const QueueCtl* ctl = reinterpret_cast<const QueueCtl*>(out + sizeof(DevResult) * h->num_graphs);
+    const uint64_t* hist = reinterpret_cast<const uint64_t*>(out + sizeof(DevResult) * h->num_graphs + sizeof(QueueCtl));
+    if (ctl_out) *ctl_out = *ctl;
+    for (uint32_t i = 0; i < h->num_graphs; i++) {
+        if (h->desc[i].n == 0) fill_empty_graph(first, last, &res[i]);
+        else fill_result(h, i, r[i], hist, &res[i]);
+    }
+    return MCE_OK;
+}
+
+int ensure_events(mce_graph_s* h)
+{
+    for (auto& e : h->ev)
+        if (!e) HIP_TRY(hipEventCreate(&e));
+    return MCE_OK;
+}
+
+// Run one solve (count, count_range or enumerate) synchronously.
+int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, hipStream_t s,
+              uint32_t* verts, uint64_t verts_cap, uint64_t* offs, uint64_t offs_cap,
+              QueueCtl* ctl_out, bool use_graph, uint32_t blocks_cap = 0)
+{
+    int rc = ensure_events(g);
+    if (rc != MCE_OK) return rc;
+    uint32_t floor = 0;
+    for (int attempt = 0; attempt < 3; attempt++) {
+        LaunchCfg c;
+        if ((rc = make_cfg(g, &c, floor, blocks_cap)) != MCE_OK) return rc;
+        if ((rc = ensure_workspace(g, c)) != MCE_OK) return rc;
+        SearchParams sp = make_params(g, c);
+        const bool enumerate = verts != nullptr || offs != nullptr;
+        if (enumerate) {
+            sp.enumerate = 1;
+            sp.verts = verts;
+            sp.verts_cap = verts ? verts_cap : 0;
+            sp.offs = reinterpret_cast<unsigned long long*>(offs);
+            sp.offs_cap = offs ? offs_cap : 0;
+        }
+        auto t0 = std::chrono::steady_clock::now();
+        (void)t0;
+        HIP_TRY(hipEventRecord(g->ev[0], s));
+        if (use_graph && !enumerate && first == 0 && last == UINT64_MAX) {
+            if (!g->graph_exec || !(g->graph_cfg == c)) {
+                if (g->graph_exec) {
+                    (void)hipGraphExecDestroy(g->graph_exec);
+                    g->graph_exec = nullptr;
+                }
+                hipStream_t cs;
+                HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    rc = enqueue_solve(g, c, sp, first, last, cs, false);
+                    e = hipStreamEndCapture(cs, &graph);
+                }
+                (void)hipStreamDestroy(cs);
+                if (e != hipSuccess || rc != MCE_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return rc != MCE_OK ? rc : hip_status(e);
+                }
+                e = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) {
+                    g->graph_exec = nullptr;
+                    return hip_status(e);
+                }
+                g->graph_cfg = c;
+            }
+            HIP_TRY(hipGraphLaunch(g->graph_exec, s));
+        } else {
+            if ((rc = enqueue_solve(g, c, sp, first, last, s, true)) != MCE_OK) return rc;
+        }
+        HIP_TRY(hipEventRecord(g->ev[1], s));
+        HIP_TRY(hipStreamSynchronize(s));
+        QueueCtl ctl;
+        read_results(g, first, last, res, &ctl);
+        if (ctl.error & kErrSpill) {
+            floor = c.blocks * c.wpb; // one chunk for every wavefront
+            continue;
+        }
+        if (ctl.error) {
+            if (ctl.error & kErrWatchdog) std::fprintf(stderr, "libmce: search stopped by the watchdog\n");
+            return MCE_E_DEVICE;
+        }
+        if (ctl_out) *ctl_out = ctl;
+        float ms = 0.f;
+        mce_stats_t st;
+        std::memset(&st, 0, sizeof(st));
+        if (hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess) st.search_us = ms * 1000.0;
+        if (!(use_graph && !enumerate && first == 0 && last == UINT64_MAX) &&
+            hipEventElapsedTime(&ms, g->ev[2], g->ev[3]) == hipSuccess)
+            st.search_kernel_us = ms * 1000.0;
+        st.prepare_us = g->prepare_ms * 1000.0;
+        st.blocks = c.blocks;
+        st.waves_per_block = c.wpb;
+        st.lds_depth = c.lds_depth;
+        st.lds_bytes_per_block = c.wave_lds_words * 4u * c.wpb;
+        st.donations = ctl.donations;
+        st.units = ctl.units;
+        st.spills = ctl.spill_levels_written;
+        t_stats = st;
+        return MCE_OK;
+    }
+    return MCE_E_NOMEM;
+}
+
+} // namespace
+
+// ================================================================ C ABI ==
+
+static int finish_prepare_timing_locked(mce_graph_t g)
+{
+    if (g->prepared_timed) return MCE_OK;
+    HIP_TRY(hipEventSynchronize(g->ev[1]));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess) g->prepare_ms = ms;
+    g->prepared_timed = true;
+    return MCE_OK;
+}
+
+extern "C" {
+
+const char* mce_strerror(int code)
+{
+    switch (code) {
+    case MCE_OK: return "ok";
+    case MCE_PENDING: return "pending";
+    case MCE_E_INVAL: return "invalid argument or non-simple graph";
+    case MCE_E_NOMEM: return "out of memory";
+    case MCE_E_TRUNCATED: return "output buffer too small";
+    case MCE_E_DEVICE: return "HIP error or no gfx950 device";
+    case MCE_E_BUSY: return "busy";
+    case MCE_E_CANCELLED: return "cancelled";
+    default: return "unknown status";
+    }
+}
+
+int mce_set_option(int key, int64_t value)
+{
+    std::lock_guard<std::mutex> lk(g_opt_mu);
+    switch (key) {
+    case MCE_OPT_WAVES_PER_BLOCK:
+        if (value < 0 || value > 16) return MCE_E_INVAL;
+        g_opt.waves_per_block = value;
+        return MCE_OK;
+    case MCE_OPT_BLOCKS:
+        if (value < 0 || value > (1 << 20)) return MCE_E_INVAL;
+        g_opt.blocks = value;
+        return MCE_OK;
+    case MCE_OPT_LDS_DEPTH:
+        if (value < -1 || value > 64) return MCE_E_INVAL;
+        g_opt.lds_depth = value;
+        return MCE_OK;
+    case MCE_OPT_SPLIT_THRESHOLD:
+        if (value < 0 || value > (1 << 30)) return MCE_E_INVAL;
+        g_opt.split_threshold = value;
+        return MCE_OK;
+    case MCE_OPT_CHECK_INTERVAL:
+        if (value < 0 || value > (1 << 30)) return MCE_E_INVAL;
+        g_opt.check_interval = value;
+        return MCE_OK;
+    case MCE_OPT_QUEUE_CAP:
+        if (value < 0 || value > (1 << 26) || (value & (value - 1))) return MCE_E_INVAL;
+        g_opt.queue_cap = value;
+        return MCE_OK;
+    case MCE_OPT_WATCHDOG_MS:
+        if (value < 0) return MCE_E_INVAL;
+        g_opt.watchdog_ms = value;
+        return MCE_OK;
+    case MCE_OPT_GRAPH:
+        if (value < 0 || value > 2) return MCE_E_INVAL;
+        g_opt.graph = value;
+        return MCE_OK;
+    default: return MCE_E_INVAL;
+    }
+}
+
+int mce_get_option(int key, int64_t* value)
+{
+    if (!value) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_opt_mu);
+    switch (key) {
+    case MCE_OPT_WAVES_PER_BLOCK: *value = g_opt.waves_per_block; return MCE_OK;
+    case MCE_OPT_BLOCKS: *value = g_opt.blocks; return MCE_OK;
+    case MCE_OPT_LDS_DEPTH: *value = g_opt.lds_depth; return MCE_OK;
+    case MCE_OPT_SPLIT_THRESHOLD: *value = g_opt.split_threshold; return MCE_OK;
+    case MCE_OPT_CHECK_INTERVAL: *value = g_opt.check_interval; return MCE_OK;
+    case MCE_OPT_QUEUE_CAP: *value = g_opt.queue_cap; return MCE_OK;
+    case MCE_OPT_WATCHDOG_MS: *value = g_opt.watchdog_ms; return MCE_OK;
+    case MCE_OPT_GRAPH: *value = g_opt.graph; return MCE_OK;
+    default: return MCE_E_INVAL;
+    }
+}
+
+int mce_last_stats(mce_stats_t* out)
+{
+    if (!out) return MCE_E_INVAL;
+    *out = t_stats;
+    return MCE_OK;
+}
+
+int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_batch_t* batch,
+                uint32_t flags, void* hip_stream, mce_graph_t* out)
+{
+    if (!out) return MCE_E_INVAL;
+    *out = nullptr;
+    if (flags & ~MCE_F_DEVICE_PTR) return MCE_E_INVAL;
+    const bool dev_ptr = (flags & MCE_F_DEVICE_PTR) != 0;
+    std::vector<GraphDesc> desc;
+    uint64_t in_words = 0;
+    // ---- shape checks and host validation (no HIP call before this) ----
+    if (!batch) {
+        if (n > MCE_MAX_N) return MCE_E_INVAL;
+        if (n > 0 && (!rows || (uint64_t)row_words * 64u < n)) return MCE_E_INVAL;
+        GraphDesc gd;
+        std::memset(&gd, 0, sizeof(gd));
+        gd.n = n;
+        gd.w32 = (n + 31) / 32;
+        gd.rw64 = n ? row_words : 0;
+        gd.in_off = 0;
+        desc.push_back(gd);
+        in_words = (uint64_t)n * (n ? row_words : 0);
+        if (!dev_ptr && n) {
+            int rc = validate_host(n, rows, row_words);
+            if (rc != MCE_OK) return rc;
+        }
+    } else {
+        if (batch->num_graphs == 0 || !batch->n || !batch->row_offset_words) return MCE_E_INVAL;
+        in_words = row_words;
+        bool any = false;
+        for (uint32_t i = 0; i < batch->num_graphs; i++) {
+            const uint32_t ni = batch->n[i];
+            if (ni > MCE_MAX_N) return MCE_E_INVAL;
+            GraphDesc gd;
+            std::memset(&gd, 0, sizeof(gd));
+            gd.n = ni;
+            gd.w32 = (ni + 31) / 32;
+            gd.rw64 = (ni + 63) / 64;
+            gd.in_off = batch->row_offset_words[i];
+            if (ni && gd.in_off + (uint64_t)ni * gd.rw64 > (uint64_t)row_words) return MCE_E_INVAL;
+            any = any || ni > 0;
+            desc.push_back(gd);
+        }
+        if (any && !rows) return MCE_E_INVAL;
+        if (!dev_ptr)
+            for (const GraphDesc& gd : desc) {
+                int rc = validate_host(gd.n, rows + gd.in_off, gd.rw64);
+                if (rc != MCE_OK) return rc;
+            }
+    }
+    // ---- device part ----
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc != MCE_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::unique_ptr<mce_graph_s> h(new mce_graph_s());
+    h->device = di.device;
+    h->num_graphs = (uint32_t)desc.size();
+    uint64_t adj = 0, ord = 0, hist = 0;
+    for (GraphDesc& gd : desc) {
+        gd.adj_off = adj;
+        gd.ord_off = ord;
+        gd.hist_off = hist;
+        adj += (uint64_t)gd.n * gd.w32;
+        ord += gd.n;
+        hist += gd.n + 1;
+        h->max_n = std::max(h->max_n, gd.n);
+        h->max_w32 = std::max(h->max_w32, gd.w32);
+    }
+    h->desc = desc;
+    h->in_words = in_words;
+    h->adj_words = adj;
+    h->ord_words = ord;
+    h->hist_total = hist;
+    if ((rc = h->d_desc.ensure(sizeof(GraphDesc) * desc.size())) != MCE_OK) return rc;
+    if ((rc = h->d_in.ensure(8 * std::max<uint64_t>(in_words, 1))) != MCE_OK) return rc;
+    if ((rc = h->d_adj.ensure(4 * std::max<uint64_t>(adj, 1))) != MCE_OK) return rc;
+    if ((rc = h->d_order.ensure(4 * std::max<uint64_t>(ord, 1))) != MCE_OK) return rc;
+    if ((rc = ensure_events(h.get())) != MCE_OK) return rc;
+    HIP_TRY(hipEventRecord(h->ev[0], s));
+    HIP_TRY(hipMemcpyAsync(h->d_desc.p, desc.data(), sizeof(GraphDesc) * desc.size(), hipMemcpyHostToDevice, s));
+    if (in_words)
+        HIP_TRY(hipMemcpyAsync(h->d_in.p, rows, 8 * in_words,
+                               dev_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (dev_ptr) {
+        // validate on the device, then wait for the verdict
+        DevBuf flag;
+        if ((rc = flag.ensure(4)) != MCE_OK) return rc;
+        HIP_TRY(hipMemsetAsync(flag.p, 0, 4, s));
+        for (const GraphDesc& gd : desc)
+            if (gd.n) HIP_TRY(launch_validate(h->d_in.as<uint64_t>() + gd.in_off, gd.n, gd.rw64, flag.as<unsigned int>(), s));
+        unsigned int bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return MCE_E_INVAL;
+    }
+    HIP_TRY(launch_order(h->d_desc.as<GraphDesc>(), h->num_graphs, h->max_n, h->d_in.as<uint64_t>(),
+                         h->d_order.as<uint32_t>(), s));
+    HIP_TRY(launch_relabel(h->d_desc.as<GraphDesc>(), h->num_graphs, h->max_n, h->d_in.as<uint64_t>(),
+                           h->d_order.as<uint32_t>(), h->d_adj.as<uint32_t>(), s));
+    HIP_TRY(hipEventRecord(h->ev[1], s));
+    *out = h.release();
+    return MCE_OK;
+}
+
+int mce_num_graphs(mce_graph_t g, uint32_t* num_graphs)
+{
+    if (!g || !num_graphs) return MCE_E_INVAL;
+    *num_graphs = g->num_graphs;
+    return MCE_OK;
+}
+
+
+int mce_get_order(mce_graph_t g, uint32_t graph_index, uint32_t* order, uint32_t cap)
+{
+    if (!g || graph_index >= g->num_graphs) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    const GraphDesc& gd = g->desc[graph_index];
+    if (gd.n && (!order || cap < gd.n)) return MCE_E_INVAL;
+    if (gd.n == 0) return MCE_OK;
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    HIP_TRY(hipMemcpy(order, g->d_order.as<uint32_t>() + gd.ord_off, 4ull * gd.n, hipMemcpyDeviceToHost));
+    return MCE_OK;
+}
+
+int mce_root_branches(mce_graph_t g, uint32_t graph_index, uint64_t* out)
+{
+    if (!g || !out || graph_index >= g->num_graphs) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    const GraphDesc& gd = g->desc[graph_index];
+    if (gd.n == 0) {
+        *out = 0;
+        return MCE_OK;
+    }
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    std::vector<uint32_t> row0(gd.w32);
+    HIP_TRY(hipMemcpy(row0.data(), g->d_adj.as<uint32_t>() + gd.adj_off, 4ull * gd.w32, hipMemcpyDeviceToHost));
+    uint64_t nb = 0;
+    for (uint32_t w = 0; w < gd.w32; w++) nb += (uint32_t)__builtin_popcount(row0[w]);
+    *out = gd.n - nb; // position 0 and its non-neighbours
+    return MCE_OK;
+}
+
+int mce_count(mce_graph_t g, mce_result_t* res, void* hip_stream)
+{
+    if (!g || !res) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    const int64_t gm = options().graph;
+    const bool use_graph = gm == 2 || (gm == 1 && g->num_graphs > 1);
+    rc = run_solve(g, 0, UINT64_MAX, res, static_cast<hipStream_t>(hip_stream), nullptr, 0, nullptr, 0,
+                   nullptr, use_graph);
+    if (rc != MCE_OK)
+        for (uint32_t i = 0; i < g->num_graphs; i++) res[i].status = rc;
+    return rc;
+}
+
+int mce_count_range(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, void* hip_stream)
+{
+    if (!g || !res || g->num_graphs != 1) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    rc = run_solve(g, first, last, res, static_cast<hipStream_t>(hip_stream), nullptr, 0, nullptr, 0,
+                   nullptr, false);
+    if (rc != MCE_OK) res->status = rc;
+    return rc;
+}
+
+int mce_enumerate(mce_graph_t g, uint32_t* verts, uint64_t verts_cap, uint64_t* offsets,
+                  uint64_t offsets_cap, uint64_t* verts_needed, uint64_t* offsets_needed,
+                  mce_result_t* res, void* hip_stream)
+{
+    if (!g || !res || g->num_graphs != 1) return MCE_E_INVAL;
+    if ((!verts && verts_cap) || (!offsets && offsets_cap)) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    if (g->desc[0].n == 0) {
+        fill_empty_graph(0, UINT64_MAX, res);
+        if (verts_needed) *verts_needed = 0;
+        if (offsets_needed) *offsets_needed = 2;
+        if (offsets_cap < 2) return MCE_E_TRUNCATED;
+        const uint64_t z[2] = {0, 0};
+        HIP_TRY(hipMemcpy(offsets, z, sizeof(z), hipMemcpyHostToDevice));
+        return MCE_OK;
+    }
+    // a non-null pointer marks enumerate mode even with zero capacity
+    static uint32_t dummy_v;
+    static uint64_t dummy_o;
+    uint32_t* v = verts ? verts : &dummy_v;
+    uint64_t* o = offsets ? offsets : &dummy_o;
+    QueueCtl ctl;
+    rc = run_solve(g, 0, UINT64_MAX, res, static_cast<hipStream_t>(hip_stream), v, verts ? verts_cap : 0,
+                   o, offsets ? offsets_cap : 0, &ctl, false);
+    if (rc != MCE_OK) {
+        res->status = rc;
+        return rc;
+    }
+    if (verts_needed) *verts_needed = ctl.vcursor;
+    if (offsets_needed) *offsets_needed = ctl.ocursor;
+    if (ctl.vcursor > verts_cap || ctl.ocursor > offsets_cap) {
+        res->status = MCE_E_TRUNCATED;
+        return MCE_E_TRUNCATED;
+    }
+    return MCE_OK;
+}
+
+int mce_release(mce_graph_t g)
+{
+    if (!g) return MCE_OK;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        (void)hipDeviceSynchronize();
+    }
+    delete g;
+    return MCE_OK;
+}
+
+} // extern "C"
+
+// ------------------------------------------------------------ serving ----
+//
+// Jobs are admitted from a host FIFO into a fixed number of device slots as
+// slots and HBM free up.  Each slot owns a non-blocking stream and runs its
+// job's persistent search on a share of the device's workgroups, so jobs
+// that arrive while others run overlap with them on the device.
+
+namespace {
+
+struct Job {
+    uint64_t ticket = 0;
+    mce_graph_t g = nullptr;
+    int state = 0; // 0 queued, 1 running, 2 done, 3 cancelled
+    int status = MCE_OK;
+    mce_result_t res;
+    std::vector<uint64_t> hist;
+    uint64_t footprint = 0;
+};
+
+constexpr uint32_t kSlots = 4;
+constexpr size_t kMaxQueued = 1u << 16;
+
+struct Server {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Job>> fifo;
+    std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;
+    std::vector<std::thread> workers;
+    uint64_t next_ticket = 1;
+    uint64_t hbm_budget = 0, hbm_used = 0;
+    uint32_t blocks_total = 0;
+    bool started = false, stop = false;
+    int device = -1;
+    ~Server()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv_work.notify_all();
+        for (auto& t : workers)
+            if (t.joinable()) t.join();
+    }
+};
+
+Server& server()
+{
+    static Server s;
+    return s;
+}
+
+// Device memory a job of this handle needs beyond what the handle holds.
+uint64_t job_footprint(mce_graph_s* h)
+{
+    LaunchCfg c;
+    if (make_cfg(h, &c, 0) != MCE_OK) return 0;
+    const uint64_t rec_words = kRecHeader + 4ull * c.w32cap;
+    return sizeof(DevResult) * h->num_graphs + 8ull * h->hist_total + 4ull * c.cap * (1 + rec_words) +
+           4ull * c.slot_words * c.spill_levels * c.spill_chunks;
+}
+
+void worker_loop(uint32_t slot)
+{
+    Server& sv = server();
+    (void)hipSetDevice(sv.device);
+    hipStream_t s = nullptr;
+    (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    for (;;) {
+        std::shared_ptr<Job> job;
+        {
+            std::unique_lock<std::mutex> lk(sv.mu);
+            for (;;) {
+                if (sv.stop) break;
+                // first queued job that fits in the HBM budget (FIFO otherwise)
+                for (auto it = sv.fifo.begin(); it != sv.fifo.end(); ++it) {
+                    if ((*it)->state != 0) continue;
+                    if (sv.hbm_used + (*it)->footprint <= sv.hbm_budget || sv.hbm_used == 0) {
+                        job = *it;
+                        sv.fifo.erase(it);
+                        break;
+                    }
+                }
+                // drop cancelled entries at the front
+                while (!sv.fifo.empty() && sv.fifo.front()->state == 3) sv.fifo.pop_front();
+                if (job) break;
+                sv.cv_work.wait(lk);
+            }
+            if (!job) break;
+            job->state = 1;
+            sv.hbm_used += job->footprint;
+        }
+        const uint32_t share = std::max<uint32_t>(sv.blocks_total / kSlots, 1u);
+        int rc;
+        {
+            std::lock_guard<std::mutex> hl(job->g->mu);
+            rc = finish_prepare_timing_locked(job->g);
+            if (rc == MCE_OK)
+                rc = run_solve(job->g, 0, UINT64_MAX, &job->res, s, nullptr, 0, nullptr, 0, nullptr, false,
+                               share);
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv.mu);
+            job->status = rc;
+            job->res.status = rc;
+            job->state = 2;
+            sv.hbm_used -= job->footprint;
+        }
+        sv.cv_done.notify_all();
+        sv.cv_work.notify_all();
+        (void)slot;
+    }
+    if (s) (void)hipStreamDestroy(s);
+}
+
+int server_start()
+{
+    Server& sv = server();
+    if (sv.started) return MCE_OK;
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc != MCE_OK) return rc;
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    sv.device = di.device;
+    sv.hbm_budget = free_b / 2;
+    int bpc = 0;
+    HIP_TRY(search_occupancy(64, 4, (kWaveFixedWords + 16 * 193) * 16, &bpc));
+    sv.blocks_total = (uint32_t)di.cus * (uint32_t)std::max(bpc, 1);
+    for (uint32_t i = 0; i < kSlots; i++) sv.workers.emplace_back(worker_loop, i);
+    sv.started = true;
+    return MCE_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int mce_submit(mce_graph_t g, uint32_t flags, uint64_t* ticket)
+{
+    if (!g || !ticket || flags != 0 || g->num_graphs != 1) return MCE_E_INVAL;
+    Server& sv = server();
+    auto job = std::make_shared<Job>();
+    job->g = g;
+    std::memset(&job->res, 0, sizeof(job->res));
+    job->hist.assign(g->desc[0].n + 1, 0);
+    job->res.hist = job->hist.data();
+    job->res.hist_len = (uint32_t)job->hist.size();
+    {
+        std::lock_guard<std::mutex> hl(g->mu);
+        job->footprint = job_footprint(g);
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv.mu);
+        int rc = server_start();
+        if (rc != MCE_OK) return rc;
+        if (sv.fifo.size() >= kMaxQueued) return MCE_E_BUSY;
+        job->ticket = sv.next_ticket++;
+        sv.jobs[job->ticket] = job;
+        sv.fifo.push_back(job);
+        *ticket = job->ticket;
+    }
+    sv.cv_work.notify_one();
+    return MCE_OK;
+}
+
+int mce_poll(uint64_t ticket, mce_result_t* res, int32_t timeout_us)
+{
+    if (!res) return MCE_E_INVAL;
+    Server& sv = server();
+    std::unique_lock<std::mutex> lk(sv.mu);
+    auto it = sv.jobs.find(ticket);
+    if (it == sv.jobs.end()) return MCE_E_INVAL;
+    std::shared_ptr<Job> job = it->second;
+    auto done = [&] { return job->state >= 2; };
+    if (!done()) {
+        if (timeout_us == 0) return MCE_PENDING;
+        if (timeout_us < 0) sv.cv_done.wait(lk, done);
+        else if (!sv.cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) return MCE_PENDING;
+    }
+    sv.jobs.erase(it);
+    if (job->state == 3) return MCE_E_CANCELLED;
+    if (job->status != MCE_OK) return job->status;
+    uint64_t* user_hist = res->hist;
+    const uint32_t user_len = res->hist_len;
+    *res = job->res;
+    res->hist = user_hist;
+    res->hist_len = user_len;
+    if (user_hist)
+        for (uint32_t k = 0; k < user_len; k++) user_hist[k] = k < job->hist.size() ? job->hist[k] : 0;
+    return MCE_OK;
+}
+
+int mce_cancel(uint64_t ticket)
+{
+    Server& sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.jobs.find(ticket);
+    if (it == sv.jobs.end()) return MCE_E_INVAL;
+    if (it->second->state == 0) {
+        it->second->state = 3;
+        sv.cv_done.notify_all();
+        return MCE_OK;
+    }
+    return MCE_E_BUSY;
+}
+
+} // extern "C"

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact on every
+integer it reports (count, size histogram, both hashes, omega, nodes, children,
+dead ends) and on the ordering.  All calls go through the C ABI (ctypes)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("count", "nodes", "children", "dead_ends", "hash_xor", "hash_sum", "omega", "hist")
+
+
+def same(gpu: dict, ref: dict, keys=KEYS):
+    for k in keys:
+        assert gpu[k] == ref[k], "%s: gpu %r != oracle %r" % (k, gpu[k], ref[k])
+
+
+@pytest.fixture(autouse=True)
+def _defaults(mce):
+    # every search in these tests stops (and fails) after 60 s instead of hanging
+    mce.reset_options(watchdog_ms=60000)
+    yield
+    mce.reset_options(watchdog_ms=60000)
+
+
+def solve(mce, rows):
+    g = mce.Graph(rows)
+    try:
+        return g.count(), g
+    except Exception:
+        g.release()
+        raise
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_gnp_100_05(mce, orc, seed):
+    rows = synth.gnp(100, 0.5, seed)
+    res, g = solve(mce, rows)
+    assert list(g.order()) == list(orc.order(rows))
+    same(res, orc.greedy(rows))
+    g.release()
+
+
+@pytest.mark.parametrize("n,p,seed", [(31, 0.5, 1), (32, 0.5, 2), (33, 0.6, 3), (63, 0.7, 4),
+                                      (64, 0.3, 5), (65, 0.8, 6), (127, 0.5, 7), (129, 0.6, 8),
+                                      (200, 0.1, 9), (300, 0.4, 10), (513, 0.2, 11)])
+def test_ragged_sizes(mce, orc, n, p, seed):
+    rows = synth.gnp(n, p, seed)
+    res, g = solve(mce, rows)
+    assert list(g.order()) == list(orc.order(rows))
+    same(res, orc.greedy(rows))
+    g.release()
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 33, 64, 65, 100])
+def test_complete_and_empty(mce, orc, n):
+    for rows in (synth.complete(n), synth.empty(n)):
+        res, g = solve(mce, rows)
+        same(res, orc.greedy(rows))
+        g.release()
+
+
+def test_moon_moser_small(mce, orc):
+    for k in (1, 2, 5, 8):
+        rows = synth.moon_moser(k)
+        res, g = solve(mce, rows)
+        same(res, orc.greedy(rows))
+        assert res["count"] == 3 ** k
+        g.release()
+
+
+def test_large_n_two_words_per_lane(mce, orc):
+    # n > 2048 takes the two-words-per-lane path
+    for n, p, seed in [(2049, 0.01, 1), (3000, 0.005, 2), (4096, 0.004, 3)]:
+        rows = synth.gnp(n, p, seed)
+        res, g = solve(mce, rows)
+        assert list(g.order()) == list(orc.order(rows))
+        same(res, orc.greedy(rows, threads=8))
+        g.release()
+
+
+def test_range_sums(mce, orc):
+    rows = synth.gnp(150, 0.5, 3)
+    g = mce.Graph(rows)
+    nb = g.root_branches()
+    assert nb == orc.root_branches(rows)
+    full = g.count()
+    cuts = [0, 1, nb // 3, nb // 2, nb - 1, nb]
+    tot = {k: 0 for k in ("count", "nodes", "children", "dead_ends", "hash_sum")}
+    x = 0
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        part = g.count_range(a, b)
+        same(part, orc.greedy_range(rows, a, b))
+        for k in tot:
+            tot[k] += part[k]
+        x ^= part["hash_xor"]
+    tot["hash_sum"] %= 1 << 64
+    for k in tot:
+        assert tot[k] == full[k]
+    assert x == full["hash_xor"]
+    g.release()
+
+
+def test_enumerate_lists(mce, orc):
+    import torch
+    for rows in (synth.gnp(60, 0.5, 1), synth.gnp(120, 0.3, 2), synth.moon_moser(4)):
+        g = mce.Graph(rows)
+        res, verts, offs = g.enumerate()
+        assert not res["truncated"]
+        ref, ref_list = orc.greedy_list(rows)
+        same(res, ref)
+        got = sorted(mce.cliques_from_output(verts, offs, res["count"]))
+        assert got == sorted(ref_list)
+        g.release()
+        torch.cuda.synchronize()
+
+
+def test_enumerate_truncated(mce, orc):
+    import torch
+    rows = synth.gnp(80, 0.5, 5)
+    g = mce.Graph(rows)
+    dev = torch.device("cuda")
+    verts = torch.zeros(4, dtype=torch.int32, device=dev)
+    offs = torch.zeros(2, dtype=torch.int64, device=dev)
+    res, _, _ = g.enumerate(verts, offs)
+    ref = orc.greedy(rows)
+    assert res["truncated"]
+    same(res, ref)
+    assert res["offsets_needed"] == 2 * ref["count"]
+    assert res["verts_needed"] == sum(k * c for k, c in enumerate(ref["hist"]))
+    g.release()
+
+
+def test_batch_matches_single(mce, orc):
+    specs = synth.batch_mix(48, 7)
+    graphs = [synth.gnp(n, p, s) for n, p, s in specs]
+    graphs += [synth.complete(5), synth.empty(0), synth.empty(7), synth.moon_moser(3)]
+    b = mce.Graph(batch=graphs)
+    out = b.count()
+    assert len(out) == len(graphs)
+    for i, rows in enumerate(graphs):
+        same(out[i], orc.greedy(rows))
+        if rows.shape[0]:
+            assert list(b.order(i)) == list(orc.order(rows))
+    b.release()
+
+
+@pytest.mark.parametrize("opts", [
+    {"lds_depth": 0},
+    {"lds_depth": 1, "check_interval": 1, "split_threshold": 1 << 20},
+    {"waves_per_block": 1, "blocks": 3},
+    {"check_interval": 1, "split_threshold": 1 << 20, "queue_cap": 64},
+    {"waves_per_block": 16, "lds_depth": 2},
+])
+def test_schedule_stress(mce, orc, opts):
+    rows = synth.gnp(120, 0.6, 11)
+    ref = orc.greedy(rows)
+    for k, v in opts.items():
+        mce.set_option(k, v)
+    res, g = solve(mce, rows)
+    same(res, ref)
+    g.release()
+
+
+def test_repeat_determinism(mce):
+    rows = synth.gnp(200, 0.5, 4)
+    g = mce.Graph(rows)
+    first = g.count()
+    for _ in range(3):
+        assert g.count() == first
+    g.release()
+
+
+def test_device_pointer_input(mce, orc):
+    import torch
+    rows = synth.gnp(90, 0.4, 8)
+    t = torch.from_numpy(rows.view(np.int64)).cuda()
+    g = mce.Graph(t)
+    same(g.count(), orc.greedy(rows))
+    g.release()
+    bad = rows.copy()
+    bad[4, 0] |= np.uint64(1 << 4)
+    with pytest.raises(mce.MceError) as e:
+        mce.Graph(torch.from_numpy(bad.view(np.int64)).cuda())
+    assert e.value.code == mce.E_INVAL
+
+
+def test_serving_alone_equals_mix(mce, orc):
+    specs = synth.serving_mix(12, 3, n_hi=400)
+    graphs = [synth.gnp(n, p, s) for n, p, s in specs]
+    handles = [mce.Graph(r) for r in graphs]
+    alone = [h.count() for h in handles]
+    tickets = [mce.submit(h) for h in handles]
+    for t, h, r, a in zip(tickets, handles, graphs, alone):
+        rc, res = mce.poll(t, r.shape[0], -1)
+        assert rc == mce.OK
+        same(res, a)
+        same(res, orc.greedy(r))
+    for h in handles:
+        h.release()
