@@ -62,13 +62,16 @@ extern "C" {
 #define MCE_OPT_WAVES_PER_BLOCK 1  /* search wavefronts per workgroup, 1..16 (0 = auto) */
 #define MCE_OPT_BLOCKS 2           /* persistent search workgroups (0 = fill the device) */
 #define MCE_OPT_LDS_DEPTH 3        /* stack levels kept in LDS per wavefront, 0..64 (rest spill to HBM) */
-#define MCE_OPT_SPLIT_THRESHOLD 4  /* donate work while the queue holds fewer units than this */
+#define MCE_OPT_SPLIT_THRESHOLD 4  /* hand over only frames whose P holds at least this many
+                                      vertices (0 = auto) */
 #define MCE_OPT_CHECK_INTERVAL 5   /* children between two looks at the queue, >= 1 */
 #define MCE_OPT_QUEUE_CAP 6        /* queue capacity in units (power of two, 0 = auto) */
 #define MCE_OPT_WATCHDOG_MS 7      /* stop a search after this many ms and fail with
                                       MCE_E_DEVICE (0 = no limit, the default) */
 #define MCE_OPT_GRAPH 8            /* mce_count replays a captured hipGraph of the solve:
                                       0 never, 1 for batch handles (default), 2 always */
+#define MCE_OPT_REFRESH_CHILDREN 9 /* children a busy workgroup processes between two looks
+                                      for hungry workgroups (0 = auto) */
 
 typedef struct mce_graph_s *mce_graph_t; /* opaque; owns the device copy, order and rows */
 

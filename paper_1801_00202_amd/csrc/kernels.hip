@@ -73,6 +73,9 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x)
     return x;
 }
 
+// Sum over the 64 lanes.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) { return rdlane(wave_scan_incl(x), 63); }
+
 // Maximum over the 64 lanes (same pattern; zero is the identity for keys).
 __device__ __forceinline__ uint32_t wave_max(uint32_t x)
 {
@@ -184,20 +187,46 @@ __device__ __forceinline__ uint32_t popc_scan(const uint32_t (&s)[WPL], uint32_t
 }
 
 // ---------------------------------------------------------------- queue ---
-
-// Bounded MPMC queue (sequence number per slot; D. Vyukov's design).  Slot
+//
+// Bounded MPMC queue (one sequence number per slot, after D. Vyukov).  Slot
 // seq == pos: free for the producer of ticket pos; seq == pos + 1: holds the
 // unit of ticket pos.  Lane 0 runs the protocol; the wavefront moves the data.
+//
+// Coherence across the XCDs' separate L2 caches: every word that crosses
+// wavefronts (records, sequence numbers, counters) is read and written with
+// device-scope accesses (sc1), which bypass the non-coherent cache levels, and
+// a wait for all outstanding vector memory operations (vmcnt(0)) separates the
+// record from the sequence number that publishes or frees it.  No L2
+// write-back or invalidate is ever issued, so the adjacency rows cached in L2
+// stay put.
+
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t* p)
+{
+    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until every vector memory access issued so far has completed.
+__device__ __forceinline__ void vm_drain()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); // no compiler motion across
+    __builtin_amdgcn_s_waitcnt(0x0F70);                     // vmcnt(0)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ __forceinline__ bool q_pop(const SearchParams& sp, uint32_t lane, uint32_t* out)
 {
     uint32_t pos = 0, ok = 0;
     if (lane == 0) {
         unsigned int* head = &sp.ctl->head;
-        pos = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pos = ld_dev(head);
         for (;;) {
-            uint32_t seq = __hip_atomic_load(&sp.seq[pos & sp.cap_mask], __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-            int32_t dif = (int32_t)(seq - (pos + 1u));
+            const uint32_t seq = ld_dev(&sp.seq[pos & sp.cap_mask]);
+            const int32_t dif = (int32_t)(seq - (pos + 1u));
             if (dif == 0) {
                 if (__hip_atomic_compare_exchange_weak(head, &pos, pos + 1u, __ATOMIC_RELAXED,
                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -207,13 +236,20 @@ __device__ __forceinline__ bool q_pop(const SearchParams& sp, uint32_t lane, uin
             } else if (dif < 0) {
                 break; // empty
             } else {
-                pos = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pos = ld_dev(head);
             }
         }
     }
     ok = bcast0(ok);
     *out = bcast0(pos);
     return ok != 0;
+}
+
+// Hand a slot back to producers once its record has been read.
+__device__ __forceinline__ void q_release_slot(const SearchParams& sp, uint32_t lane, uint32_t pos)
+{
+    vm_drain();
+    if (lane == 0) st_dev(&sp.seq[pos & sp.cap_mask], pos + sp.cap_mask + 1u);
 }
 
 template <int WPL>
@@ -224,11 +260,10 @@ __device__ bool q_push(const SearchParams& sp, uint32_t lane, uint32_t g, uint32
     uint32_t pos = 0, ok = 0;
     if (lane == 0) {
         unsigned int* tail = &sp.ctl->tail;
-        pos = __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pos = ld_dev(tail);
         for (;;) {
-            uint32_t seq = __hip_atomic_load(&sp.seq[pos & sp.cap_mask], __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-            int32_t dif = (int32_t)(seq - pos);
+            const uint32_t seq = ld_dev(&sp.seq[pos & sp.cap_mask]);
+            const int32_t dif = (int32_t)(seq - pos);
             if (dif == 0) {
                 if (__hip_atomic_compare_exchange_weak(tail, &pos, pos + 1u, __ATOMIC_RELAXED,
                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -238,31 +273,32 @@ __device__ bool q_push(const SearchParams& sp, uint32_t lane, uint32_t g, uint32
             } else if (dif < 0) {
                 break; // full
             } else {
-                pos = __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pos = ld_dev(tail);
             }
         }
-        if (ok) __hip_atomic_fetch_add(&sp.ctl->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ok) __hip_atomic_fetch_add(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     ok = bcast0(ok);
     pos = bcast0(pos);
     if (!ok) return false;
     uint32_t* r = sp.rec + (size_t)(pos & sp.cap_mask) * sp.rec_words;
     const uint32_t cs = sp.w32cap;
-    if (lane == 0) r[0] = g;
+    if (lane == 0) st_dev(&r[0], g);
 #pragma unroll
     for (int c = 0; c < WPL; c++) {
         const uint32_t w = (uint32_t)c * 64u + lane;
         if (w < W) {
-            r[kRecHeader + w] = Rb[c];
-            r[kRecHeader + cs + w] = P[c];
-            r[kRecHeader + 2 * cs + w] = X[c];
-            r[kRecHeader + 3 * cs + w] = L[c];
+            st_dev(&r[kRecHeader + w], Rb[c]);
+            st_dev(&r[kRecHeader + cs + w], P[c]);
+            st_dev(&r[kRecHeader + 2 * cs + w], X[c]);
+            st_dev(&r[kRecHeader + 3 * cs + w], L[c]);
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0)
-        __hip_atomic_store(&sp.seq[pos & sp.cap_mask], pos + 1u, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    vm_drain();
+    if (lane == 0) {
+        st_dev(&sp.seq[pos & sp.cap_mask], pos + 1u);
+        __hip_atomic_fetch_add(&sp.ctl->board, 1ull << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     return true;
 }
 
@@ -362,7 +398,8 @@ __global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, co
 }
 
 // Zero the per-graph results and the control block; seq[i] = i (all slots free).
-__global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist_total, uint32_t cap)
+__global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist_total, uint32_t cap,
+                             uint32_t workgroups)
 {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -372,6 +409,7 @@ __global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist
     for (uint64_t i = tid; i < hist_total; i += stride) sp.hist[i] = 0ull;
     for (uint64_t i = tid; i < cap; i += stride) sp.seq[i] = (unsigned int)i;
     if (tid < sizeof(QueueCtl) / 8) reinterpret_cast<unsigned long long*>(sp.ctl)[tid] = 0ull;
+    (void)workgroups; // set by the root kernel, after this kernel has cleared the block
 }
 
 // Root of each graph (R = {}, P = V, X = {}): its pivot is the first vertex
@@ -380,9 +418,14 @@ __global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist
 // earlier children, L = the selected children.  The root node counts iff
 // first == 0.  One wavefront per graph.
 template <int WPL>
-__global__ void __launch_bounds__(64) root_kernel(SearchParams sp, uint64_t first, uint64_t last)
+__global__ void __launch_bounds__(64) root_kernel(SearchParams sp, uint64_t first, uint64_t last,
+                                                  uint32_t workgroups)
 {
     const uint32_t g = blockIdx.x;
+    // every workgroup of the search starts out waiting for work
+    if (g == 0 && threadIdx.x == 0)
+        __hip_atomic_fetch_add(&sp.ctl->board, (unsigned long long)workgroups, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     const GraphDesc gd = sp.graphs[g];
     const uint32_t n = gd.n;
     if (n == 0) return;
@@ -401,7 +444,7 @@ __global__ void __launch_bounds__(64) root_kernel(SearchParams sp, uint64_t firs
     const uint32_t total = popc_scan<WPL>(L0, cnt, incl);
     if (lane == 0) {
         sp.results[g].root_branches = total;
-        if (first == 0) atomicAdd(&sp.results[g].nodes, 1ull);
+        if (first == 0 && last > 0) atomicAdd(&sp.results[g].nodes, 1ull);
     }
     const uint32_t lo = first < (uint64_t)total ? (uint32_t)first : total;
     const uint32_t hi = last < (uint64_t)total ? (uint32_t)last : total;
@@ -422,222 +465,624 @@ __global__ void __launch_bounds__(64) root_kernel(SearchParams sp, uint64_t firs
     q_push<WPL>(sp, lane, g, W, Rb, P, X, L);
 }
 
-// The persistent search.  See the header comment for the layout.
-template <int WPL>
-__global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
+// ------------------------------------------------------ the search -------
+//
+// Scheduling is two-level, so that the hot path touches no shared HBM word:
+//   * inside a workgroup, wavefronts share a small LIFO of units in LDS.  A
+//     busy wavefront looks at two LDS counters every check_interval children
+//     and, while siblings wait and the LIFO is short, hands over half of the
+//     candidates of its shallowest frame;
+//   * between workgroups, units move through the HBM queue.  Only a workgroup
+//     whose wavefronts are all idle fetches from it, and busy workgroups
+//     publish to it only while the LDS snapshot of the number of hungry
+//     workgroups (refreshed by one wavefront per workgroup every
+//     refresh period) says some are waiting.
+// Termination: ctl->work counts the units in the HBM queue plus the
+// workgroups that hold work (running or in their LDS LIFO); the search is over
+// when it reaches zero.
+
+struct WgHdr {
+    uint32_t lock;      // LDS spin lock over the LIFO and the counters below
+    uint32_t busy;      // wavefronts holding a unit
+    uint32_t lq_n;      // units in the LIFO
+    uint32_t active;    // this workgroup is counted in ctl->work
+    uint32_t fetcher;   // a wavefront is fetching from the HBM queue
+    uint32_t done;      // stop: search over or aborted
+    uint32_t snap;      // global donations still wanted (snapshot)
+    uint32_t ticks;     // children processed by the workgroup, in steps of check_interval
+    uint32_t pad[8];
+};
+static_assert(sizeof(WgHdr) == kWgHdrWords * 4, "header size");
+
+__device__ __forceinline__ uint32_t lds_ld(uint32_t* p)
 {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Take the workgroup lock.  Returns false only if the search deadline passed
+// while waiting; the caller then abandons the search.
+__device__ __forceinline__ bool wg_lock(WgHdr* h, uint32_t lane, uint64_t t_start, uint64_t limit)
+{
+    uint32_t ok = 1;
+    if (lane == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_exchange(&h->lock, 1u, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u) {
+            __builtin_amdgcn_s_sleep(1);
+            if (limit != 0 && (++spins & 1023u) == 0 && (uint64_t)wall_clock64() - t_start > limit) {
+                ok = 0;
+                break;
+            }
+        }
+    }
+    ok = bcast0(ok);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return ok != 0;
+}
+
+__device__ __forceinline__ void wg_unlock(WgHdr* h, uint32_t lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) __hip_atomic_store(&h->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Per-wavefront LDS layout (32-bit words):
+//   [kOffHist, +128)   histogram of clique sizes < kHistLds (u64)
+//   [kOffAcc,  +256)   per lane: XOR and sum of the hashes of flushed cliques (u64 each)
+//   [kOffCent, +64)    clique buffer entries: start | size << 16
+//   [kOffCids, +kCliqueIds/2)  clique buffer ids (u16)
+//   [kOffCtx,  +32)    WaveCtx: totals and bookkeeping used off the hot path
+//   [kWaveFixedWords, +slot_words)  the current frame, written before a check
+//   then lds_depth stack frames of slot_words each
+constexpr uint32_t kOffHist = 0, kOffAcc = 128, kOffCent = 384, kOffCids = 448, kOffCtx = kOffCids + kCliqueIds / 2;
+static_assert(kOffCids + kCliqueIds / 2 == kOffCtx, "layout");
+static_assert(kOffCtx + 32 == kWaveFixedWords, "layout");
+
+struct WaveCtx {
+    unsigned long long count, nodes, children; // totals of graph g not yet folded into HBM
+    unsigned long long units, donations, spills;
+    uint32_t omega, g, spill_chunk, refreshes;
+    uint32_t pad[16];
+};
+static_assert(sizeof(WaveCtx) == 32 * 4, "ctx size");
+
+__device__ __forceinline__ WaveCtx* wave_ctx(uint32_t* wl) { return reinterpret_cast<WaveCtx*>(wl + kOffCtx); }
+
+// A lane bitset passed by value to the out-of-line helpers (an array reference
+// would force it into scratch memory).
+template <int WPL> struct LaneBits {
+    uint32_t w[WPL];
+};
+
+// Hash, histogram and (enumerate) write-out of the nent buffered cliques; one
+// clique per lane.  Off the hot path.
+__device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restrict__ spp, uint32_t* wl,
+                                                     uint32_t nent_v, uint32_t used_v, uint32_t hist_off_lo,
+                                                     uint32_t hist_off_hi)
+{
+    const SearchParams& sp = *spp;
+    const uint32_t lane = lane_id();
+    const uint32_t nent = bcast0(nent_v), used = bcast0(used_v);
+    const uint64_t hoff = ((uint64_t)bcast0(hist_off_hi) << 32) | bcast0(hist_off_lo);
+    unsigned long long* ghist = sp.hist + hoff;
+    unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl + kOffHist);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(wl + kOffAcc);
+    const uint32_t* cent = wl + kOffCent;
+    const uint16_t* cids = reinterpret_cast<const uint16_t*>(wl + kOffCids);
+    WaveCtx* ctx = wave_ctx(wl);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    const bool mine = lane < nent;
+    const uint32_t e = mine ? cent[lane] : 0u;
+    const uint32_t st = e & 0xffffu, k = e >> 16;
+    if (mine) {
+        uint64_t h = mix64((uint64_t)k);
+        for (uint32_t j = 0; j < k; j++) h = mix64(h + kGolden + (uint64_t)cids[st + j]);
+        acc[lane] ^= h;
+        acc[64 + lane] += h;
+    }
+    uint64_t rem = ballot(mine);
+    uint32_t kmax = 0;
+    while (rem) {
+        const uint32_t l0 = (uint32_t)__builtin_ctzll(rem);
+        const uint32_t k0 = rdlane(k, l0);
+        const uint64_t m = ballot(mine && k == k0);
+        const uint32_t c = (uint32_t)__builtin_popcountll(m);
+        if (lane == 0) {
+            if (k0 < kHistLds) hist_l[k0] += c;
+            else atomicAdd(&ghist[k0], (unsigned long long)c);
+        }
+        kmax = umax32(kmax, k0);
+        rem &= ~m;
+    }
+    if (lane == 0) {
+        ctx->count += nent;
+        ctx->omega = umax32(ctx->omega, kmax);
+    }
+    if (sp.enumerate) {
+        unsigned long long vb = 0, ob = 0;
+        if (lane == 0) {
+            vb = atomicAdd(&sp.ctl->vcursor, (unsigned long long)used);
+            ob = atomicAdd(&sp.ctl->ocursor, 2ull * nent);
+        }
+        vb = ((unsigned long long)bcast0((uint32_t)(vb >> 32)) << 32) | bcast0((uint32_t)vb);
+        ob = ((unsigned long long)bcast0((uint32_t)(ob >> 32)) << 32) | bcast0((uint32_t)ob);
+        if (vb + used <= sp.verts_cap && ob + 2ull * nent <= sp.offs_cap) {
+            for (uint32_t i = lane; i < used; i += 64) sp.verts[vb + i] = cids[i];
+            if (mine) {
+                sp.offs[ob + 2ull * lane] = vb + st;
+                sp.offs[ob + 2ull * lane + 1ull] = vb + st + k;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+}
+
+// A clique too large for the buffer: hashed in place on the scalar unit.
+template <int WPL>
+__device__ __attribute__((noinline)) void cold_big_clique(const SearchParams* __restrict__ spp, uint32_t* wl,
+                                                          LaneBits<WPL> cwb, uint32_t hist_off_lo,
+                                                          uint32_t hist_off_hi)
+{
+    const uint32_t (&cw)[WPL] = cwb.w;
+    const SearchParams& sp = *spp;
+    const uint32_t lane = lane_id();
+    const uint64_t hoff = ((uint64_t)bcast0(hist_off_hi) << 32) | bcast0(hist_off_lo);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(wl + kOffAcc);
+    WaveCtx* ctx = wave_ctx(wl);
+    uint32_t cnt[WPL], incl[WPL];
+    const uint32_t k = popc_scan<WPL>(cw, cnt, incl);
+    uint64_t h = mix64((uint64_t)k);
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        uint64_t m = ballot(cw[c] != 0);
+        while (m) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            uint32_t w = rdlane(cw[c], l);
+            while (w) {
+                const uint32_t b = (uint32_t)__builtin_ctz(w);
+                w &= w - 1;
+                h = mix64(h + kGolden + (uint64_t)((((uint32_t)c * 64u + l) << 5) | b));
+            }
+        }
+    }
+    if (lane == 0) {
+        acc[0] ^= h;
+        acc[64] += h;
+        atomicAdd(&sp.hist[hoff + k], 1ull);
+        ctx->count += 1;
+        ctx->omega = umax32(ctx->omega, k);
+    }
+    if (sp.enumerate) {
+        unsigned long long vb = 0, ob = 0;
+        if (lane == 0) {
+            vb = atomicAdd(&sp.ctl->vcursor, (unsigned long long)k);
+            ob = atomicAdd(&sp.ctl->ocursor, 2ull);
+        }
+        vb = ((unsigned long long)bcast0((uint32_t)(vb >> 32)) << 32) | bcast0((uint32_t)vb);
+        ob = ((unsigned long long)bcast0((uint32_t)(ob >> 32)) << 32) | bcast0((uint32_t)ob);
+        if (vb + k <= sp.verts_cap && ob + 2ull <= sp.offs_cap) {
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                uint64_t p = vb + incl[c] - cnt[c];
+                uint32_t x = cw[c];
+                const uint32_t wb = ((uint32_t)c * 64u + lane) << 5;
+                while (x) {
+                    sp.verts[p++] = wb | (uint32_t)__builtin_ctz(x);
+                    x &= x - 1;
+                }
+            }
+            if (lane == 0) {
+                sp.offs[ob] = vb;
+                sp.offs[ob + 1] = vb + k;
+            }
+        }
+    }
+}
+
+// Fold the wavefront's totals of graph ctx->g into HBM and clear them.
+__device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restrict__ spp, uint32_t* wl)
+{
+    const SearchParams& sp = *spp;
+    const uint32_t lane = lane_id();
+    WaveCtx* ctx = wave_ctx(wl);
+    const uint32_t g = bcast0(ctx->g);
+    if (g == 0xffffffffu) return;
+    unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl + kOffHist);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(wl + kOffAcc);
+    uint64_t x = acc[lane], s = acc[64 + lane];
+    acc[lane] = 0;
+    acc[64 + lane] = 0;
+    for (int off = 32; off > 0; off >>= 1) {
+        x ^= __shfl_xor(x, off);
+        s += __shfl_xor(s, off);
+    }
+    const uint64_t hoff = sp.graphs[g].hist_off;
+    if (lane == 0) {
+        DevResult* r = sp.results + g;
+        if (ctx->count) atomicAdd(&r->count, ctx->count);
+        if (ctx->nodes) atomicAdd(&r->nodes, ctx->nodes);
+        if (ctx->children) atomicAdd(&r->children, ctx->children);
+        if (x) atomicXor(&r->hash_xor, (unsigned long long)x);
+        if (s) atomicAdd(&r->hash_sum, (unsigned long long)s);
+        if (ctx->omega) atomicMax(&r->omega, ctx->omega);
+        ctx->count = ctx->nodes = ctx->children = 0;
+        ctx->omega = 0;
+    }
+    for (uint32_t i = lane; i < kHistLds; i += 64) {
+        const unsigned long long hv = hist_l[i];
+        if (hv) {
+            atomicAdd(&sp.hist[hoff + i], hv);
+            hist_l[i] = 0ull;
+        }
+    }
+}
+
+// The look at siblings and at the board every check_interval children.  The
+// current frame is in its LDS slot; frames 0..d-1 are on the stack.  May hand
+// the later half of the candidates of the shallowest big-enough frame to the
+// LDS LIFO or to the HBM queue (the current frame's L in its slot is updated
+// then).  Returns 1 if the search must stop.
+template <int WPL>
+__device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __restrict__ spp, uint32_t* smem,
+                                                         uint32_t* wl, uint32_t d_v, uint32_t W_v, uint32_t g_v,
+                                                         LaneBits<WPL> Rbb, uint64_t t_start, uint32_t refresh_v)
+{
+    const uint32_t (&Rb)[WPL] = Rbb.w;
+    const SearchParams& sp = *spp;
+    const uint32_t lane = lane_id();
+    const uint32_t d = bcast0(d_v), W = bcast0(W_v), g = bcast0(g_v);
+    const uint32_t NW = blockDim.x >> 6;
+    WgHdr* hdr = reinterpret_cast<WgHdr*>(smem);
+    uint32_t* lq = smem + kWgHdrWords;
+    WaveCtx* ctx = wave_ctx(wl);
+    const uint32_t SW = sp.slot_words, CS = sp.w32cap, RW = sp.rec_words;
+    uint32_t* cur = wl + kWaveFixedWords;
+    uint32_t* stk = cur + SW;
+    const uint32_t chunk = bcast0(ctx->spill_chunk);
+    auto frame = [&](uint32_t s) -> uint32_t* {
+        if (s == d) return cur;
+        if (s < sp.lds_depth) return stk + (size_t)s * SW;
+        return sp.spill + ((size_t)chunk * sp.spill_levels + (s - sp.lds_depth)) * SW;
+    };
+    if (bcast0(lds_ld(&hdr->done))) return 1;
+    const uint32_t busy = bcast0(lds_ld(&hdr->busy));
+    const uint32_t lqn = bcast0(lds_ld(&hdr->lq_n));
+    // Where to hand work: first to siblings that wait for it, then to hungry
+    // workgroups, and otherwise keep one unit in stock in the LIFO so that a
+    // wavefront that finishes finds work at once.
+    const bool siblings_wait = lqn < kLocalSlots && NW - busy > lqn;
+    bool to_local = siblings_wait;
+    bool to_global = false;
+    if (!to_local && bcast0(lds_ld(&hdr->snap)) != 0u) {
+        uint32_t got = 0;
+        if (lane == 0) {
+            uint32_t sv = lds_ld(&hdr->snap);
+            while (sv != 0u && !__hip_atomic_compare_exchange_weak(&hdr->snap, &sv, sv - 1u, __ATOMIC_RELAXED,
+                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            }
+            got = sv != 0u;
+        }
+        to_global = bcast0(got) != 0u;
+    }
+    if (!to_local && !to_global && lqn == 0u) to_local = true;
+    if (to_local || to_global) {
+        for (uint32_t s = 0; s <= d; s++) {
+            const uint32_t* f = frame(s);
+            uint32_t Ls[WPL], Ps[WPL], Xs[WPL], cnt[WPL], incl[WPL];
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t w = (uint32_t)c * 64u + lane;
+                Ls[c] = (w < W) ? f[2 * CS + w] : 0u;
+            }
+            const uint32_t tot = popc_scan<WPL>(Ls, cnt, incl);
+            if (tot < 2) continue;
+            uint32_t pc = 0;
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t w = (uint32_t)c * 64u + lane;
+                Ps[c] = (w < W) ? f[w] : 0u;
+                Xs[c] = (w < W) ? f[CS + w] : 0u;
+                pc += (uint32_t)__builtin_popcount(Ps[c]);
+            }
+            // frames below are smaller still
+            if (wave_sum(pc) < sp.split_threshold) break;
+            const uint32_t keep = (tot + 1u) / 2u;
+            uint32_t L1[WPL], L2[WPL], Pd[WPL], Xd[WPL], Rs[WPL];
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t before = incl[c] - cnt[c];
+                L1[c] = low_bits(Ls[c], rank_take(keep, before, cnt[c]));
+                L2[c] = Ls[c] & ~L1[c];
+                Pd[c] = Ps[c] & ~L1[c];
+                Xd[c] = Xs[c] | L1[c];
+                Rs[c] = Rb[c];
+            }
+            // R of frame s: drop the children pushed from frames s..d-1
+            for (uint32_t j = s; j < d; j++) clear_bit<WPL>(Rs, bcast0(frame(j)[3 * CS]), lane);
+            bool ok;
+            if (to_global) {
+                ok = q_push<WPL>(sp, lane, g, W, Rs, Pd, Xd, L2);
+            } else {
+                if (!wg_lock(hdr, lane, t_start, sp.watchdog_ticks)) return 1;
+                const uint32_t n = bcast0(lds_ld(&hdr->lq_n));
+                ok = n < kLocalSlots;
+                if (ok) {
+                    uint32_t* r = lq + (size_t)n * RW;
+                    if (lane == 0) r[0] = g;
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) {
+                        const uint32_t w = (uint32_t)c * 64u + lane;
+                        if (w < W) {
+                            r[kRecHeader + w] = Rs[c];
+                            r[kRecHeader + CS + w] = Pd[c];
+                            r[kRecHeader + 2 * CS + w] = Xd[c];
+                            r[kRecHeader + 3 * CS + w] = L2[c];
+                        }
+                    }
+                    if (lane == 0) lds_st(&hdr->lq_n, n + 1);
+                }
+                wg_unlock(hdr, lane);
+            }
+            if (ok) {
+                uint32_t* fw = frame(s);
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    const uint32_t w = (uint32_t)c * 64u + lane;
+                    if (w < W) fw[2 * CS + w] = L1[c];
+                }
+                if (lane == 0) ctx->donations += 1;
+            }
+            break;
+        }
+    }
+    // Refresh the snapshot of hungry workgroups (the caller decides when: once
+    // per refresh_children children of the workgroup; paced by work done, not
+    // by a clock, because the real-time counter is slow to read from thousands
+    // of wavefronts).
+    if (bcast0(refresh_v)) {
+        uint32_t e = 0, rf = 0;
+        if (lane == 0) {
+            const unsigned long long b = __hip_atomic_load(&sp.ctl->board, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t hg = (uint32_t)b, q = (uint32_t)(b >> 32);
+            lds_st(&hdr->snap, hg > q ? umin32(hg - q, 2u) : 0u);
+            rf = ++ctx->refreshes;
+            if ((rf & 7u) == 0u) e = ld_dev(&sp.ctl->error);
+        }
+        rf = bcast0(rf);
+        const bool late = (rf & 63u) == 0u && sp.watchdog_ticks != 0 &&
+                          (uint64_t)wall_clock64() - t_start > sp.watchdog_ticks;
+        if (late && lane == 0) atomicOr(&sp.ctl->error, kErrWatchdog);
+        if (bcast0(e) != 0u || late) {
+            if (lane == 0) lds_st(&hdr->done, 1u);
+            return 1;
+        }
+    }
+    return 0;
+}
+
+template <int WPL>
+__global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const SearchParams* __restrict__ spp)
+{
+    // sp (by value) serves the hot path, where its pointers are known to be
+    // global; spp, the same block in HBM, is handed to the out-of-line helpers.
     extern __shared__ uint32_t smem[];
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x >> 6;
-    uint32_t* wl = smem + (size_t)wv * sp.wave_lds_words;
-    unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl);
-    uint32_t* cent = wl + kHistLds * 2;
-    uint16_t* cids = reinterpret_cast<uint16_t*>(cent + kCliqueEntries);
-    uint32_t* stk = cent + kCliqueEntries + kCliqueIds / 2;
-    const uint32_t SW = sp.slot_words, CS = sp.w32cap;
-    uint32_t* spill = nullptr;  // this wavefront's chunk of the spill pool, taken on first use
+    const uint32_t NW = blockDim.x >> 6;
+    WgHdr* hdr = reinterpret_cast<WgHdr*>(smem);
+    uint32_t* lq = smem + kWgHdrWords;
+    const uint32_t RW = sp.rec_words;
+    uint32_t* wl = lq + kLocalSlots * RW + (size_t)wv * sp.wave_lds_words;
+    WaveCtx* ctx = wave_ctx(wl);
 
-    for (uint32_t i = lane; i < kHistLds; i += 64) hist_l[i] = 0ull;
+    if (threadIdx.x < kWgHdrWords) smem[threadIdx.x] = 0u;
+    for (uint32_t i = lane; i < kWaveFixedWords; i += 64) wl[i] = 0u;
+    if (lane == 0) {
+        ctx->g = 0xffffffffu;
+        ctx->spill_chunk = 0xffffffffu;
+    }
+    __syncthreads();
 
     const uint64_t t_start = wall_clock64();
     auto overdue = [&]() -> bool {
         return sp.watchdog_ticks != 0 && wall_clock64() - t_start > sp.watchdog_ticks;
     };
-    uint64_t acc_x = 0, acc_s = 0;                 // per lane: hashes of flushed cliques
-    uint32_t nent = 0, used = 0;                   // clique buffer fill (uniform)
-    uint64_t c_nodes = 0, c_children = 0, c_dead = 0, c_count = 0;
-    uint32_t c_omega = 0;
-    uint64_t n_units = 0, n_don = 0, n_spill = 0;
+    auto give_up = [&]() {
+        if (lane == 0) {
+            atomicOr(&sp.ctl->error, kErrWatchdog);
+            lds_st(&hdr->done, 1u);
+        }
+    };
+    const uint32_t gwave = blockIdx.x * NW + wv;
+    auto set_state = [&](uint32_t st) {
+        if (lane == 0 && sp.wave_state) sp.wave_state[gwave] = st;
+    };
+    set_state(kWaveIdle);
 
+    uint32_t backoff = 1, fetch_iters = 0, idle_iters = 0, polls = 1;
     for (;;) {
-        uint32_t pos;
-        if (!q_pop(sp, lane, &pos)) {
-            uint32_t pend = 0, err = 0;
-            if (lane == 0) {
-                pend = __hip_atomic_load(&sp.ctl->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                err = __hip_atomic_load(&sp.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // ================= obtain a unit =================
+        // 1: from the LDS LIFO (slot lsl), 2: from HBM (ticket pos)
+        uint32_t src = 0, lsl = 0, pos = 0;
+        bool stop = false;
+        for (;;) {
+            // Look without the lock first; take it only when there is something to do.
+            {
+                const uint32_t n0 = bcast0(lds_ld(&hdr->lq_n));
+                const uint32_t dn0 = bcast0(lds_ld(&hdr->done));
+                const uint32_t f0 = bcast0(lds_ld(&hdr->fetcher));
+                const uint32_t b0 = bcast0(lds_ld(&hdr->busy));
+                if (n0 == 0u && dn0 == 0u && (f0 != 0u || b0 != 0u)) {
+                    if ((++idle_iters & 255u) == 0u && overdue()) {
+                        give_up();
+                        stop = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(16);
+                    continue;
+                }
             }
-            pend = bcast0(pend);
-            err = bcast0(err);
-            if (pend == 0 || err != 0) break;
-            if (overdue()) {
-                if (lane == 0) atomicOr(&sp.ctl->error, kErrWatchdog);
+            if (((++idle_iters & 255u) == 0u && overdue()) || !wg_lock(hdr, lane, t_start, sp.watchdog_ticks)) {
+                give_up();
+                stop = true;
                 break;
             }
-            __builtin_amdgcn_s_sleep(8);
-            continue;
+            const uint32_t n = bcast0(lds_ld(&hdr->lq_n));
+            if (n > 0) {
+                lsl = n - 1;
+                if (lane == 0) {
+                    lds_st(&hdr->lq_n, n - 1);
+                    lds_st(&hdr->busy, lds_ld(&hdr->busy) + 1);
+                }
+                src = 1;
+                break; // still holding the lock: the record is copied below
+            }
+            if (bcast0(lds_ld(&hdr->done))) {
+                wg_unlock(hdr, lane);
+                stop = true;
+                break;
+            }
+            uint32_t fetch = 0, went_inactive = 0;
+            if (lane == 0 && lds_ld(&hdr->fetcher) == 0u) {
+                lds_st(&hdr->fetcher, 1u);
+                fetch = 1;
+                if (lds_ld(&hdr->busy) == 0u && lds_ld(&hdr->active) != 0u) {
+                    lds_st(&hdr->active, 0u);
+                    went_inactive = 1;
+                }
+                if (lds_ld(&hdr->active) != 0u) fetch = 2; // siblings still busy: wait locally
+            }
+            wg_unlock(hdr, lane);
+            fetch = bcast0(fetch);
+            if (bcast0(went_inactive) && lane == 0) {
+                __hip_atomic_fetch_add(&sp.ctl->board, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (fetch == 1) {
+                set_state(kWaveFetch);
+                // look at the board once per poll_iters idle iterations
+                bool try_pop = false;
+                if (++fetch_iters >= sp.poll_iters) {
+                    fetch_iters = 0;
+                    polls++;
+                    unsigned long long b = 0;
+                    if (lane == 0) b = __hip_atomic_load(&sp.ctl->board, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    try_pop = bcast0((uint32_t)(b >> 32)) != 0u;
+                }
+                if (try_pop && q_pop(sp, lane, &pos)) {
+                    uint32_t was_active = 0;
+                    if (!wg_lock(hdr, lane, t_start, sp.watchdog_ticks)) {
+                        give_up();
+                        stop = true;
+                        break;
+                    }
+                    if (lane == 0) {
+                        was_active = lds_ld(&hdr->active);
+                        lds_st(&hdr->active, 1u);
+                        lds_st(&hdr->busy, lds_ld(&hdr->busy) + 1);
+                        lds_st(&hdr->fetcher, 0u);
+                    }
+                    wg_unlock(hdr, lane);
+                    if (lane == 0) {
+                        if (was_active) { // the unit's count is already covered by this workgroup
+                            __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_fetch_sub(&sp.ctl->board, 1ull << 32, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            __hip_atomic_fetch_sub(&sp.ctl->board, (1ull << 32) + 1ull, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                    src = 2;
+                    break;
+                }
+                if ((polls & 1u) == 0u) {
+                    polls++;
+                    uint32_t w = 0, e = 0;
+                    if (lane == 0) {
+                        w = ld_dev(&sp.ctl->work);
+                        e = ld_dev(&sp.ctl->error);
+                    }
+                    w = bcast0(w);
+                    e = bcast0(e);
+                    const bool late = (polls & 63u) == 0u && overdue();
+                    if (late && lane == 0) atomicOr(&sp.ctl->error, kErrWatchdog);
+                    if (lane == 0) {
+                        if (w == 0u || e != 0u || late) lds_st(&hdr->done, 1u);
+                        lds_st(&hdr->fetcher, 0u);
+                    }
+                    if (w == 0u || e != 0u || late) {
+                        stop = true;
+                        break;
+                    }
+                } else if (lane == 0) {
+                    lds_st(&hdr->fetcher, 0u);
+                }
+            } else if (fetch == 2 && lane == 0) {
+                lds_st(&hdr->fetcher, 0u);
+            }
+            for (uint32_t i = 0; i < backoff; i++) __builtin_amdgcn_s_sleep(8);
+            if (backoff < 8) backoff <<= 1;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const uint32_t* rec = sp.rec + (size_t)(pos & sp.cap_mask) * sp.rec_words;
-        const uint32_t g = bcast0(rec[0]);
-        const GraphDesc gd = sp.graphs[g];
-        const uint32_t W = gd.w32;
+        if (stop) break;
+        backoff = 1;
+        set_state(kWaveBusy);
+
+        // ================= load the unit =================
+        const uint32_t CS = sp.w32cap, SW = sp.slot_words;
+        const uint32_t* rec = (src == 1) ? (lq + (size_t)lsl * RW)
+                                         : (sp.rec + (size_t)(pos & sp.cap_mask) * sp.rec_words);
+        const uint32_t g = bcast0(src == 1 ? rec[0] : ld_dev(&rec[0]));
+        const uint32_t W = bcast0(sp.graphs[g].w32);
         uint32_t Rb[WPL], P[WPL], X[WPL], L[WPL], roff[WPL];
 #pragma unroll
         for (int c = 0; c < WPL; c++) {
             const uint32_t w = (uint32_t)c * 64u + lane;
             const bool in = w < W;
-            Rb[c] = in ? rec[kRecHeader + w] : 0u;
-            P[c] = in ? rec[kRecHeader + CS + w] : 0u;
-            X[c] = in ? rec[kRecHeader + 2 * CS + w] : 0u;
-            L[c] = in ? rec[kRecHeader + 3 * CS + w] : 0u;
+            if (src == 1) {
+                Rb[c] = in ? rec[kRecHeader + w] : 0u;
+                P[c] = in ? rec[kRecHeader + CS + w] : 0u;
+                X[c] = in ? rec[kRecHeader + 2 * CS + w] : 0u;
+                L[c] = in ? rec[kRecHeader + 3 * CS + w] : 0u;
+            } else {
+                Rb[c] = in ? ld_dev(&rec[kRecHeader + w]) : 0u;
+                P[c] = in ? ld_dev(&rec[kRecHeader + CS + w]) : 0u;
+                X[c] = in ? ld_dev(&rec[kRecHeader + 2 * CS + w]) : 0u;
+                L[c] = in ? ld_dev(&rec[kRecHeader + 3 * CS + w]) : 0u;
+            }
             roff[c] = in ? w : (W - 1u);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0)
-            __hip_atomic_store(&sp.seq[pos & sp.cap_mask], pos + sp.cap_mask + 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        n_units++;
+        if (src == 1) wg_unlock(hdr, lane);
+        else q_release_slot(sp, lane, pos);
+        if (g != bcast0(ctx->g)) {
+            cold_fold(spp, wl);
+            if (lane == 0) ctx->g = g;
+        }
+        if (lane == 0) ctx->units += 1;
 
+        // ================= the search of the unit (Alg. 4) =================
+        const GraphDesc& gd = sp.graphs[g];
         const uint32_t* adj = sp.adj + gd.adj_off;
         const uint32_t* ord = sp.order + gd.ord_off;
-        unsigned long long* ghist = sp.hist + gd.hist_off;
-        uint32_t d = 0;               // frames of this unit on the stack
-        uint32_t since = sp.check_interval; // look at the queue right away
+        const uint32_t hoff_lo = (uint32_t)gd.hist_off, hoff_hi = (uint32_t)(gd.hist_off >> 32);
+        const uint32_t lds_depth = sp.lds_depth;
+        const uint32_t cimask = sp.check_interval - 1u; // check_interval is a power of two
+        const uint32_t refresh_children = sp.refresh_children;
+        uint32_t* cent = wl + kOffCent;
+        uint16_t* cids = reinterpret_cast<uint16_t*>(wl + kOffCids);
+        uint32_t* cur = wl + kWaveFixedWords;
+        uint32_t* stk = cur + SW;
+        uint32_t d = 0;          // frames of this unit on the stack
+        uint32_t kids = 0;       // children examined in this unit (low 32 bits)
+        uint32_t nodes = 0;      // nodes created in this unit (low 32 bits)
+        uint32_t nent = 0, used = 0; // clique buffer fill
+        uint32_t chunk = bcast0(ctx->spill_chunk);
         bool abort = false;
-
-        // ---- clique buffer: hash, histogram and (enumerate) output ----
-        auto hist_add = [&](uint32_t k, uint32_t c) {
-            if (k < kHistLds) {
-                if (lane == 0) hist_l[k] += c;
-            } else if (lane == 0) {
-                atomicAdd(&ghist[k], (unsigned long long)c);
-            }
-        };
-        auto flush = [&]() {
-            if (nent == 0) return;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            const bool mine = lane < nent;
-            const uint32_t e = mine ? cent[lane] : 0u;
-            const uint32_t st = e & 0xffffu, k = e >> 16;
-            if (mine) {
-                uint64_t h = mix64((uint64_t)k);
-                for (uint32_t j = 0; j < k; j++) h = mix64(h + kGolden + (uint64_t)cids[st + j]);
-                acc_x ^= h;
-                acc_s += h;
-            }
-            uint64_t rem = ballot(mine);
-            while (rem) {
-                const uint32_t l0 = (uint32_t)__builtin_ctzll(rem);
-                const uint32_t k0 = rdlane(k, l0);
-                const uint64_t m = ballot(mine && k == k0);
-                hist_add(k0, (uint32_t)__builtin_popcountll(m));
-                rem &= ~m;
-            }
-            if (sp.enumerate) {
-                unsigned long long vb = 0, ob = 0;
-                if (lane == 0) {
-                    vb = atomicAdd(&sp.ctl->vcursor, (unsigned long long)used);
-                    ob = atomicAdd(&sp.ctl->ocursor, 2ull * nent);
-                }
-                vb = ((unsigned long long)bcast0((uint32_t)(vb >> 32)) << 32) | bcast0((uint32_t)vb);
-                ob = ((unsigned long long)bcast0((uint32_t)(ob >> 32)) << 32) | bcast0((uint32_t)ob);
-                if (vb + used <= sp.verts_cap && ob + 2ull * nent <= sp.offs_cap) {
-                    for (uint32_t i = lane; i < used; i += 64) sp.verts[vb + i] = cids[i];
-                    if (mine) {
-                        sp.offs[ob + 2ull * lane] = vb + st;
-                        sp.offs[ob + 2ull * lane + 1ull] = vb + st + k;
-                    }
-                }
-            }
-            c_count += nent;
-            nent = 0;
-            used = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        };
-        // Report R u {v} (idv = input id of v): R is the bitset Rb over input
-        // ids, so the clique's sorted ids are the set bits in lane order.
-        auto report = [&](uint32_t idv) {
-            uint32_t cw[WPL], cnt[WPL], incl[WPL];
-            const uint32_t iw = idv >> 5, im = 1u << (idv & 31);
-#pragma unroll
-            for (int c = 0; c < WPL; c++)
-                cw[c] = Rb[c] | (((uint32_t)c * 64u + lane == iw) ? im : 0u);
-            const uint32_t k = popc_scan<WPL>(cw, cnt, incl);
-            c_omega = umax32(c_omega, k);
-            if (k > kCliqueIds) {
-                // Very large clique: hash it in place on the scalar unit.
-                uint64_t h = mix64((uint64_t)k);
-#pragma unroll
-                for (int c = 0; c < WPL; c++) {
-                    uint64_t m = ballot(cw[c] != 0);
-                    while (m) {
-                        const uint32_t l = (uint32_t)__builtin_ctzll(m);
-                        m &= m - 1;
-                        uint32_t w = rdlane(cw[c], l);
-                        while (w) {
-                            const uint32_t b = (uint32_t)__builtin_ctz(w);
-                            w &= w - 1;
-                            h = mix64(h + kGolden + (uint64_t)((((uint32_t)c * 64u + l) << 5) | b));
-                        }
-                    }
-                }
-                if (lane == 0) {
-                    acc_x ^= h;
-                    acc_s += h;
-                }
-                hist_add(k, 1);
-                c_count += 1;
-                if (sp.enumerate) {
-                    unsigned long long vb = 0, ob = 0;
-                    if (lane == 0) {
-                        vb = atomicAdd(&sp.ctl->vcursor, (unsigned long long)k);
-                        ob = atomicAdd(&sp.ctl->ocursor, 2ull);
-                    }
-                    vb = ((unsigned long long)bcast0((uint32_t)(vb >> 32)) << 32) | bcast0((uint32_t)vb);
-                    ob = ((unsigned long long)bcast0((uint32_t)(ob >> 32)) << 32) | bcast0((uint32_t)ob);
-                    if (vb + k <= sp.verts_cap && ob + 2ull <= sp.offs_cap) {
-#pragma unroll
-                        for (int c = 0; c < WPL; c++) {
-                            uint64_t p = vb + incl[c] - cnt[c];
-                            uint32_t x = cw[c];
-                            const uint32_t wb = ((uint32_t)c * 64u + lane) << 5;
-                            while (x) {
-                                sp.verts[p++] = wb | (uint32_t)__builtin_ctz(x);
-                                x &= x - 1;
-                            }
-                        }
-                        if (lane == 0) {
-                            sp.offs[ob] = vb;
-                            sp.offs[ob + 1] = vb + k;
-                        }
-                    }
-                }
-                return;
-            }
-            if (nent == kCliqueEntries || used + k > kCliqueIds) flush();
-            const uint32_t base = used;
-#pragma unroll
-            for (int c = 0; c < WPL; c++) {
-                uint32_t p = base + incl[c] - cnt[c];
-                uint32_t x = cw[c];
-                const uint32_t wb = ((uint32_t)c * 64u + lane) << 5;
-                while (x) {
-                    cids[p++] = (uint16_t)(wb | (uint32_t)__builtin_ctz(x));
-                    x &= x - 1;
-                }
-            }
-            if (lane == 0) cent[nent] = base | (k << 16);
-            used += k;
-            nent++;
-        };
-
-        // ---- stack frames ----
-        // frame s: P, X, L of the node at depth s of this unit, after steps
-        // 12-13 for the child being explored, and the input id of that child.
-        auto spill_base = [&]() -> bool {
-            if (spill) return true;
-            uint32_t chunk = 0;
-            if (lane == 0) chunk = (uint32_t)atomicAdd(&sp.ctl->spill_next, 1ull);
-            chunk = bcast0(chunk);
-            if (chunk >= sp.spill_chunks) {
-                if (lane == 0) atomicOr(&sp.ctl->error, kErrSpill);
-                return false;
-            }
-            spill = sp.spill + (size_t)chunk * sp.spill_levels * SW;
-            return true;
-        };
-        (void)spill_base;
 
         for (;;) {
             int vi = first_bit<WPL>(L);
@@ -645,8 +1090,8 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
                 // node finished: return to the parent frame
                 if (d == 0) break;
                 d--;
-                uint32_t idv;
-                if (d < sp.lds_depth) {
+                uint32_t idp;
+                if (d < lds_depth) {
                     const uint32_t* f = stk + (size_t)d * SW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
@@ -656,9 +1101,9 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
                         X[c] = in ? f[CS + w] : 0u;
                         L[c] = in ? f[2 * CS + w] : 0u;
                     }
-                    idv = bcast0(f[3 * CS]);
+                    idp = bcast0(f[3 * CS]);
                 } else {
-                    const uint32_t* f = spill + (size_t)(d - sp.lds_depth) * SW;
+                    const uint32_t* f = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
                         const uint32_t w = (uint32_t)c * 64u + lane;
@@ -667,9 +1112,9 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
                         X[c] = in ? f[CS + w] : 0u;
                         L[c] = in ? f[2 * CS + w] : 0u;
                     }
-                    idv = bcast0(f[3 * CS]);
+                    idp = bcast0(f[3 * CS]);
                 }
-                clear_bit<WPL>(Rb, idv, lane);
+                clear_bit<WPL>(Rb, idp, lane);
                 continue;
             }
             const uint32_t v = (uint32_t)vi;
@@ -678,7 +1123,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
             uint32_t row[WPL];
 #pragma unroll
             for (int c = 0; c < WPL; c++) row[c] = rv[roff[c]];
-            const uint32_t idv = ord[v];
+            const uint32_t idv = bcast0(ord[v]);
             clear_bit<WPL>(L, v, lane);
             uint32_t P2[WPL], X2[WPL];
 #pragma unroll
@@ -689,12 +1134,13 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
             // steps 12-13 for the current node
             clear_bit<WPL>(P, v, lane);
             set_bit<WPL>(X, v, lane);
-            c_children++;
+            kids++;
             if (any_set<WPL>(P2)) {
                 // the child is a node: push the current frame, descend
-                c_nodes++;
-                if (d < sp.lds_depth) {
-                    uint32_t* f = stk + (size_t)d * SW;
+                nodes++;
+                uint32_t* f;
+                if (d < lds_depth) {
+                    f = stk + (size_t)d * SW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
                         const uint32_t w = (uint32_t)c * 64u + lane;
@@ -706,27 +1152,37 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
                     }
                     if (lane == 0) f[3 * CS] = idv;
                 } else {
-                    if (d - sp.lds_depth >= sp.spill_levels) {
+                    if (d - lds_depth >= sp.spill_levels) {
                         if (lane == 0) atomicOr(&sp.ctl->error, kErrDepth);
                         abort = true;
                         break;
                     }
-                    if (!spill_base()) {
-                        abort = true;
-                        break;
+                    if (chunk == 0xffffffffu) {
+                        uint32_t ch = 0;
+                        if (lane == 0) ch = (uint32_t)atomicAdd(&sp.ctl->spill_next, 1ull);
+                        ch = bcast0(ch);
+                        if (ch >= sp.spill_chunks) {
+                            if (lane == 0) atomicOr(&sp.ctl->error, kErrSpill);
+                            abort = true;
+                            break;
+                        }
+                        chunk = ch;
+                        if (lane == 0) ctx->spill_chunk = ch;
                     }
-                    uint32_t* f = spill + (size_t)(d - sp.lds_depth) * SW;
+                    uint32_t* fs = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
                         const uint32_t w = (uint32_t)c * 64u + lane;
                         if (w < W) {
-                            f[w] = P[c];
-                            f[CS + w] = X[c];
-                            f[2 * CS + w] = L[c];
+                            fs[w] = P[c];
+                            fs[CS + w] = X[c];
+                            fs[2 * CS + w] = L[c];
                         }
                     }
-                    if (lane == 0) f[3 * CS] = idv;
-                    n_spill++;
+                    if (lane == 0) {
+                        fs[3 * CS] = idv;
+                        ctx->spills += 1;
+                    }
                 }
                 d++;
                 set_bit<WPL>(Rb, idv, lane);
@@ -743,138 +1199,115 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp)
 #pragma unroll
                 for (int c = 0; c < WPL; c++) L[c] = P[c] & ~rp[roff[c]];
             } else if (!any_set<WPL>(X2)) {
-                report(idv); // P' and X' empty: R u {v} is maximal
-            } else {
-                c_dead++;
+                // P' and X' empty: R u {v} is maximal.  R is the bitset Rb over
+                // input ids, so the clique's sorted ids are its set bits in
+                // lane order.
+                uint32_t cw[WPL], cnt[WPL], incl[WPL];
+                const uint32_t iw = idv >> 5, im = 1u << (idv & 31);
+#pragma unroll
+                for (int c = 0; c < WPL; c++) cw[c] = Rb[c] | (((uint32_t)c * 64u + lane == iw) ? im : 0u);
+                const uint32_t k = popc_scan<WPL>(cw, cnt, incl);
+                if (k > kCliqueIds) {
+                    LaneBits<WPL> cwb;
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) cwb.w[c] = cw[c];
+                    cold_big_clique<WPL>(spp, wl, cwb, hoff_lo, hoff_hi);
+                } else {
+                    if (nent == kCliqueEntries || used + k > kCliqueIds) {
+                        cold_flush(spp, wl, nent, used, hoff_lo, hoff_hi);
+                        nent = 0;
+                        used = 0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) {
+                        uint32_t p = used + incl[c] - cnt[c];
+                        uint32_t x = cw[c];
+                        const uint32_t wb = ((uint32_t)c * 64u + lane) << 5;
+                        while (x) {
+                            cids[p++] = (uint16_t)(wb | (uint32_t)__builtin_ctz(x));
+                            x &= x - 1;
+                        }
+                    }
+                    if (lane == 0) cent[nent] = used | (k << 16);
+                    used += k;
+                    nent++;
+                }
             }
 
-            // ---- work donation ----
-            if (++since >= sp.check_interval) {
-                since = 0;
-                uint32_t qs = 0, err = 0;
+            if ((kids & cimask) == 0u) {
+                // Look at the siblings (LDS only); call the out-of-line handler
+                // only when there is something to do.
                 if (lane == 0) {
-                    const uint32_t t = __hip_atomic_load(&sp.ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const uint32_t h = __hip_atomic_load(&sp.ctl->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    err = __hip_atomic_load(&sp.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    qs = t - h;
+                    __hip_atomic_fetch_add(&ctx->nodes, (unsigned long long)nodes, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    __hip_atomic_fetch_add(&ctx->children, (unsigned long long)kids, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
                 }
-                qs = bcast0(qs);
-                if (bcast0(err) != 0) {
+                nodes = 0;
+                kids = 0;
+                const uint32_t busy = bcast0(lds_ld(&hdr->busy));
+                const uint32_t lqn = bcast0(lds_ld(&hdr->lq_n));
+                const uint32_t dn = bcast0(lds_ld(&hdr->done));
+                const uint32_t snap = bcast0(lds_ld(&hdr->snap));
+                uint32_t tk = 0;
+                if (lane == 0)
+                    tk = __hip_atomic_fetch_add(&hdr->ticks, cimask + 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+                tk = bcast0(tk);
+                const uint32_t refresh = (tk / refresh_children) != ((tk + cimask + 1u) / refresh_children);
+                if (dn) {
                     abort = true;
                     break;
                 }
-                if (overdue()) {
-                    if (lane == 0) atomicOr(&sp.ctl->error, kErrWatchdog);
-                    abort = true;
-                    break;
-                }
-                if (qs < sp.split_threshold) {
-                    // shallowest frame with at least two candidates left
-                    for (uint32_t s = 0; s <= d; s++) {
-                        uint32_t Ls[WPL], Ps[WPL], Xs[WPL];
-                        const uint32_t* f = nullptr;
-                        bool in_lds = s < sp.lds_depth;
-                        if (s == d) {
+                if (refresh || snap || lqn == 0u || (lqn < kLocalSlots && NW - busy > lqn)) {
 #pragma unroll
-                            for (int c = 0; c < WPL; c++) {
-                                Ls[c] = L[c];
-                                Ps[c] = P[c];
-                                Xs[c] = X[c];
-                            }
-                        } else {
-                            f = in_lds ? (stk + (size_t)s * SW) : (spill + (size_t)(s - sp.lds_depth) * SW);
-#pragma unroll
-                            for (int c = 0; c < WPL; c++) {
-                                const uint32_t w = (uint32_t)c * 64u + lane;
-                                Ls[c] = (w < W) ? f[2 * CS + w] : 0u;
-                            }
+                    for (int c = 0; c < WPL; c++) {
+                        const uint32_t w = (uint32_t)c * 64u + lane;
+                        if (w < W) {
+                            cur[w] = P[c];
+                            cur[CS + w] = X[c];
+                            cur[2 * CS + w] = L[c];
                         }
-                        uint32_t cnt[WPL], incl[WPL];
-                        const uint32_t tot = popc_scan<WPL>(Ls, cnt, incl);
-                        if (tot < 2) continue;
-                        if (s != d) {
+                    }
+                    LaneBits<WPL> rbb;
 #pragma unroll
-                            for (int c = 0; c < WPL; c++) {
-                                const uint32_t w = (uint32_t)c * 64u + lane;
-                                Ps[c] = (w < W) ? f[w] : 0u;
-                                Xs[c] = (w < W) ? f[CS + w] : 0u;
-                            }
-                        }
-                        const uint32_t keep = (tot + 1u) / 2u;
-                        uint32_t L1[WPL], L2[WPL], Pd[WPL], Xd[WPL], Rs[WPL];
-#pragma unroll
-                        for (int c = 0; c < WPL; c++) {
-                            const uint32_t before = incl[c] - cnt[c];
-                            const uint32_t nk = rank_take(keep, before, cnt[c]);
-                            L1[c] = low_bits(Ls[c], nk);
-                            L2[c] = Ls[c] & ~L1[c];
-                            Pd[c] = Ps[c] & ~L1[c];
-                            Xd[c] = Xs[c] | L1[c];
-                            Rs[c] = Rb[c];
-                        }
-                        // R of frame s: drop the children pushed from frames s..d-1
-                        for (uint32_t j = s; j < d; j++) {
-                            const uint32_t* fj = (j < sp.lds_depth) ? (stk + (size_t)j * SW)
-                                                                    : (spill + (size_t)(j - sp.lds_depth) * SW);
-                            clear_bit<WPL>(Rs, bcast0(fj[3 * CS]), lane);
-                        }
-                        if (q_push<WPL>(sp, lane, g, W, Rs, Pd, Xd, L2)) {
-                            n_don++;
-                            if (s == d) {
-#pragma unroll
-                                for (int c = 0; c < WPL; c++) L[c] = L1[c];
-                            } else {
-                                uint32_t* fw = in_lds ? (stk + (size_t)s * SW)
-                                                      : (spill + (size_t)(s - sp.lds_depth) * SW);
-#pragma unroll
-                                for (int c = 0; c < WPL; c++) {
-                                    const uint32_t w = (uint32_t)c * 64u + lane;
-                                    if (w < W) fw[2 * CS + w] = L1[c];
-                                }
-                            }
-                        }
+                    for (int c = 0; c < WPL; c++) rbb.w[c] = Rb[c];
+                    if (bcast0(cold_check<WPL>(spp, smem, wl, d, W, g, rbb, t_start, refresh))) {
+                        abort = true;
                         break;
                     }
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) {
+                        const uint32_t w = (uint32_t)c * 64u + lane;
+                        L[c] = (w < W) ? cur[2 * CS + w] : 0u;
+                    }
+                    chunk = bcast0(ctx->spill_chunk);
                 }
             }
         }
 
-        // ---- unit finished: fold its totals into graph g ----
-        flush();
-        {
-            uint64_t x = acc_x, s = acc_s;
-            for (int off = 32; off > 0; off >>= 1) {
-                x ^= __shfl_xor(x, off);
-                s += __shfl_xor(s, off);
-            }
-            if (lane == 0) {
-                DevResult* r = sp.results + g;
-                if (c_count) atomicAdd(&r->count, (unsigned long long)c_count);
-                if (c_nodes) atomicAdd(&r->nodes, (unsigned long long)c_nodes);
-                if (c_children) atomicAdd(&r->children, (unsigned long long)c_children);
-                if (c_dead) atomicAdd(&r->dead_ends, (unsigned long long)c_dead);
-                if (x) atomicXor(&r->hash_xor, (unsigned long long)x);
-                if (s) atomicAdd(&r->hash_sum, (unsigned long long)s);
-                if (c_omega) atomicMax(&r->omega, c_omega);
-            }
-            for (uint32_t i = lane; i < kHistLds; i += 64) {
-                const unsigned long long hv = hist_l[i];
-                if (hv) {
-                    atomicAdd(&ghist[i], hv);
-                    hist_l[i] = 0ull;
-                }
-            }
-            acc_x = acc_s = 0;
-            c_count = c_nodes = c_children = c_dead = 0;
-            c_omega = 0;
+        // ---- unit finished ----
+        if (nent) cold_flush(spp, wl, nent, used, hoff_lo, hoff_hi);
+        if (lane == 0) {
+            ctx->nodes += nodes;
+            ctx->children += kids;
         }
-        if (lane == 0) __hip_atomic_fetch_sub(&sp.ctl->pending, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        set_state(kWaveIdle);
+        if (!wg_lock(hdr, lane, t_start, sp.watchdog_ticks)) {
+            give_up();
+            break;
+        }
+        if (lane == 0) lds_st(&hdr->busy, lds_ld(&hdr->busy) - 1);
+        if (abort && lane == 0) lds_st(&hdr->done, 1u);
+        wg_unlock(hdr, lane);
         if (abort) break;
     }
+    cold_fold(spp, wl);
+    set_state(kWaveExited);
     if (lane == 0) {
-        if (n_units) atomicAdd(&sp.ctl->units, (unsigned long long)n_units);
-        if (n_don) atomicAdd(&sp.ctl->donations, (unsigned long long)n_don);
-        if (n_spill) atomicAdd(&sp.ctl->spill_levels_written, (unsigned long long)n_spill);
+        if (ctx->units) atomicAdd(&sp.ctl->units, ctx->units);
+        if (ctx->donations) atomicAdd(&sp.ctl->donations, ctx->donations);
+        if (ctx->spills) atomicAdd(&sp.ctl->spill_levels_written, ctx->spills);
     }
 }
 
@@ -917,7 +1350,7 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
 }
 
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
-                        uint32_t cap, hipStream_t s)
+                        uint32_t cap, uint32_t workgroups, hipStream_t s)
 {
     uint64_t work = hist_total;
     if (work < cap) work = cap;
@@ -925,17 +1358,17 @@ hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hi
     uint32_t blocks = (uint32_t)((work + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, sp, num_graphs, hist_total, cap);
+    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, sp, num_graphs, hist_total, cap, workgroups);
     return hipGetLastError();
 }
 
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
-                       uint64_t first, uint64_t last, hipStream_t s)
+                       uint64_t first, uint64_t last, uint32_t workgroups, hipStream_t s)
 {
     if (max_w32 <= 64)
-        hipLaunchKernelGGL(root_kernel<1>, dim3(num_graphs), dim3(64), 0, s, sp, first, last);
+        hipLaunchKernelGGL(root_kernel<1>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, workgroups);
     else
-        hipLaunchKernelGGL(root_kernel<2>, dim3(num_graphs), dim3(64), 0, s, sp, first, last);
+        hipLaunchKernelGGL(root_kernel<2>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, workgroups);
     return hipGetLastError();
 }
 
@@ -956,16 +1389,16 @@ static hipError_t ensure_search_attr()
     return err;
 }
 
-hipError_t launch_search(const SearchParams& sp, uint32_t max_w32, uint32_t blocks,
+hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s)
 {
-    const uint32_t lds = sp.wave_lds_words * 4u * waves_per_block;
+    const uint32_t lds = search_lds_bytes(sp.wave_lds_words, sp.rec_words, waves_per_block);
     hipError_t e = ensure_search_attr();
     if (e != hipSuccess) return e;
     if (max_w32 <= 64)
-        hipLaunchKernelGGL(search_kernel<1>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp);
+        hipLaunchKernelGGL(search_kernel<1>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp, d_sp);
     else
-        hipLaunchKernelGGL(search_kernel<2>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp);
+        hipLaunchKernelGGL(search_kernel<2>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp, d_sp);
     return hipGetLastError();
 }
 

@@ -10,15 +10,20 @@ namespace mce {
 constexpr uint32_t kMaxN = 4096;
 // Per-wavefront clique buffer in LDS: sorted input ids (u16) of cliques waiting
 // to be hashed, and one entry word (start | size << 16) per clique.
-constexpr uint32_t kCliqueIds = 1024;
+constexpr uint32_t kCliqueIds = 512;
 constexpr uint32_t kCliqueEntries = 64;
 // Per-wavefront LDS histogram; larger clique sizes go straight to HBM.
 constexpr uint32_t kHistLds = 64;
 // Words at the head of a queue record (graph index, spare).
 constexpr uint32_t kRecHeader = 2;
-// LDS words of a wavefront before its stack window:
-// hist (kHistLds u64) + entries (kCliqueEntries u32) + ids (kCliqueIds u16).
-constexpr uint32_t kWaveFixedWords = kHistLds * 2 + kCliqueEntries + kCliqueIds / 2;
+// Per-workgroup LDS: a header and a LIFO of units shared by its wavefronts.
+constexpr uint32_t kWgHdrWords = 16;
+constexpr uint32_t kLocalSlots = 8;
+// LDS words of a wavefront before its frames: histogram (kHistLds u64), per-lane
+// hash accumulators (2 x 64 u64), clique buffer entries (kCliqueEntries u32) and
+// ids (kCliqueIds u16), and a 32-word context block.  Then come the slot of the
+// current frame and the stack window.
+constexpr uint32_t kWaveFixedWords = kHistLds * 2 + 256 + kCliqueEntries + kCliqueIds / 2 + 32;
 
 // One graph of a handle, in device memory.
 struct GraphDesc {
@@ -39,13 +44,20 @@ struct DevResult {
     unsigned int omega, status;
 };
 
-// Control block of one search launch.
+// Control block of one search launch.  The words every workgroup polls sit
+// on cache lines of their own.
 struct QueueCtl {
-    unsigned int head, tail, pending, error;
+    unsigned int head, pad_h[31];     // HBM queue: next ticket to consume
+    unsigned int tail, pad_t[31];     // HBM queue: next ticket to produce
+    unsigned int work, pad_w[31];     // units in the HBM queue + workgroups holding work
+    unsigned long long board;         // low 32 bits: workgroups waiting for a unit from HBM,
+    unsigned long long pad_g[15];     // high 32 bits: units published in the HBM queue
+    unsigned int error, pad_e[31];
     unsigned long long donations, units;
     unsigned long long spill_next;           // next free chunk of the spill pool
     unsigned long long spill_levels_written; // stack levels stored in HBM
     unsigned long long vcursor, ocursor;     // enumerate output cursors
+    unsigned long long pad_s[2];
 };
 // QueueCtl.error bits
 constexpr unsigned int kErrSpill = 1u; // spill pool exhausted: rerun with a larger pool
@@ -77,7 +89,18 @@ struct SearchParams {
     uint32_t check_interval;
     uint32_t enumerate;
     uint64_t watchdog_ticks;  // wall-clock ticks a wavefront may run (0 = no limit)
+    uint32_t refresh_children; // children a workgroup processes between two looks at the board
+    uint32_t poll_iters;       // idle iterations between two looks of a hungry workgroup
+    uint32_t* wave_state;     // per wavefront: kWave* phase (for deadline reports), or null
 };
+// Phases recorded in SearchParams.wave_state.
+constexpr uint32_t kWaveIdle = 1, kWaveFetch = 2, kWaveBusy = 3, kWaveExited = 4;
+
+// Dynamic LDS of one search workgroup.
+inline uint32_t search_lds_bytes(uint32_t wave_lds_words, uint32_t rec_words, uint32_t waves)
+{
+    return 4u * (kWgHdrWords + kLocalSlots * rec_words + wave_lds_words * waves);
+}
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_validate(const uint64_t* rows, uint32_t n, uint32_t rw, unsigned int* flag,
@@ -88,10 +111,10 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
                           const uint64_t* rows_in, const uint32_t* order, uint32_t* adj,
                           hipStream_t s);
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
-                        uint32_t cap, hipStream_t s);
+                        uint32_t cap, uint32_t workgroups, hipStream_t s);
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
-                       uint64_t first, uint64_t last, hipStream_t s);
-hipError_t launch_search(const SearchParams& sp, uint32_t max_w32, uint32_t blocks,
+                       uint64_t first, uint64_t last, uint32_t workgroups, hipStream_t s);
+hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s);
 hipError_t search_occupancy(uint32_t max_w32, uint32_t waves_per_block, uint32_t lds_bytes,
                             int* blocks_per_cu);

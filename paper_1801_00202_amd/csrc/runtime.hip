@@ -36,6 +36,7 @@ struct Options {
     int64_t queue_cap = 0;       // 0: auto
     int64_t watchdog_ms = 0;     // 0: none
     int64_t graph = 1;           // hipGraph replay: 0 never, 1 batches, 2 always
+    int64_t refresh_children = 0; // 0: auto
 };
 
 std::mutex g_opt_mu;
@@ -292,7 +293,8 @@ struct mce_graph_s {
     uint64_t in_words = 0, adj_words = 0, ord_words = 0, hist_total = 0;
     DevBuf d_desc, d_in, d_adj, d_order;
     // workspace of the solve
-    DevBuf d_results, d_hist, d_ctl, d_seq, d_rec, d_spill;
+    DevBuf d_results, d_hist, d_ctl, d_seq, d_rec, d_spill, d_state, d_params;
+    HostPinned h_params; // staging of the search parameters (stable for graph replays)
     HostPinned h_out; // results | ctl | hist, copied back in one go
     LaunchCfg cfg;
     bool cfg_valid = false;
@@ -323,15 +325,16 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     if (rc != MCE_OK) return rc;
     const Options o = options();
     LaunchCfg c;
-    c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16) : 4u;
+    c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16) : 8u;
     c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
     c.slot_words = 3 * c.w32cap + 1;
-    uint32_t depth = o.lds_depth >= 0 ? (uint32_t)std::min<int64_t>(o.lds_depth, 64) : 16u;
+    uint32_t depth = o.lds_depth >= 0 ? (uint32_t)std::min<int64_t>(o.lds_depth, 64) : 12u;
     // keep a workgroup within the LDS limit
+    const uint32_t rec_words = kRecHeader + 4 * c.w32cap;
     for (;;) {
-        uint32_t wl = kWaveFixedWords + depth * c.slot_words;
+        uint32_t wl = kWaveFixedWords + (depth + 1) * c.slot_words;
         wl = (wl + 1u) & ~1u;
-        if ((size_t)wl * 4u * c.wpb <= di.lds_per_block || (depth == 0 && c.wpb == 1)) {
+        if (search_lds_bytes(wl, rec_words, c.wpb) <= di.lds_per_block || (depth == 0 && c.wpb == 1)) {
             c.wave_lds_words = wl;
             break;
         }
@@ -339,7 +342,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         else c.wpb--;
     }
     c.lds_depth = depth;
-    const uint32_t lds_bytes = c.wave_lds_words * 4u * c.wpb;
+    const uint32_t lds_bytes = search_lds_bytes(c.wave_lds_words, rec_words, c.wpb);
     if (o.blocks > 0) {
         c.blocks = (uint32_t)o.blocks;
     } else {
@@ -350,8 +353,8 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     }
     if (blocks_cap && c.blocks > blocks_cap) c.blocks = blocks_cap;
     const uint32_t waves = c.blocks * c.wpb;
-    c.split_threshold = o.split_threshold > 0 ? (uint32_t)o.split_threshold : std::max<uint32_t>(waves / 8u, 4u);
-    c.check_interval = o.check_interval > 0 ? (uint32_t)o.check_interval : 32u;
+    c.split_threshold = o.split_threshold > 0 ? (uint32_t)o.split_threshold : 12u;
+    c.check_interval = next_pow2(o.check_interval > 0 ? (uint64_t)o.check_interval : 32u);
     uint64_t cap = o.queue_cap > 0 ? (uint64_t)o.queue_cap
                                    : std::max<uint64_t>({(uint64_t)waves * 2u, (uint64_t)h->num_graphs * 2u, 1024u});
     cap = std::max<uint64_t>(cap, (uint64_t)h->num_graphs + 1u);
@@ -374,6 +377,9 @@ int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
     if ((rc = h->d_rec.ensure(4ull * rec_words * c.cap)) != MCE_OK) return rc;
     const uint64_t spill = 4ull * c.slot_words * c.spill_levels * c.spill_chunks;
     if ((rc = h->d_spill.ensure(spill)) != MCE_OK) return rc;
+    if ((rc = h->d_state.ensure(4ull * c.blocks * c.wpb)) != MCE_OK) return rc;
+    if ((rc = h->d_params.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
+    if ((rc = h->h_params.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
     if ((rc = h->h_out.ensure(out_bytes(h))) != MCE_OK) return rc;
     return MCE_OK;
 }
@@ -391,6 +397,7 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
     sp.seq = h->d_seq.as<unsigned int>();
     sp.rec = h->d_rec.as<uint32_t>();
     sp.spill = h->d_spill.as<uint32_t>();
+    sp.wave_state = h->d_state.as<uint32_t>();
     sp.cap_mask = c.cap - 1;
     sp.rec_words = kRecHeader + 4 * c.w32cap;
     sp.w32cap = c.w32cap;
@@ -403,8 +410,12 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
     sp.check_interval = c.check_interval;
     const Options o = options();
     DeviceInfo di;
-    if (o.watchdog_ms > 0 && device_info(&di) == MCE_OK && di.wall_khz > 0)
-        sp.watchdog_ticks = (uint64_t)o.watchdog_ms * (uint64_t)di.wall_khz;
+    const bool have_clock = device_info(&di) == MCE_OK && di.wall_khz > 0;
+    if (o.watchdog_ms > 0 && have_clock) sp.watchdog_ticks = (uint64_t)o.watchdog_ms * (uint64_t)di.wall_khz;
+    // a busy workgroup looks at the board every refresh_children children
+    sp.refresh_children = o.refresh_children > 0 ? (uint32_t)o.refresh_children : 512u;
+    if (sp.refresh_children < sp.check_interval) sp.refresh_children = sp.check_interval;
+    sp.poll_iters = 4;
     return sp;
 }
 
@@ -412,10 +423,12 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
 int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, uint64_t first,
                   uint64_t last, hipStream_t s, bool timed)
 {
-    HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.cap, s));
-    HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, s));
+    HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.cap, c.blocks, s));
+    HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, c.blocks, s));
+    std::memcpy(h->h_params.p, &sp, sizeof(sp));
+    HIP_TRY(hipMemcpyAsync(h->d_params.p, h->h_params.p, sizeof(sp), hipMemcpyHostToDevice, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
-    HIP_TRY(launch_search(sp, h->max_w32, c.blocks, c.wpb, s));
+    HIP_TRY(launch_search(sp, h->d_params.as<SearchParams>(), h->max_w32, c.blocks, c.wpb, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
     char* out = static_cast<char*>(h->h_out.p);
     HIP_TRY(hipMemcpyAsync(out, sp.results, sizeof(DevResult) * h->num_graphs, hipMemcpyDeviceToHost, s));
@@ -428,13 +441,15 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
 }
 
 void fill_result(const mce_graph_s* h, uint32_t gi, const DevResult& r, const uint64_t* hist,
-                 mce_result_t* out)
+                 bool root_counted, mce_result_t* out)
 {
     const GraphDesc& gd = h->desc[gi];
     out->count = r.count;
     out->nodes = r.nodes;
     out->children = r.children;
-    out->dead_ends = r.dead_ends;
+    // every child is a new node, a maximal clique or a dead end; the root is a
+    // node but no child
+    out->dead_ends = r.children - (r.nodes - (root_counted ? 1u : 0u)) - r.count;
     out->hash_xor = r.hash_xor;
     out->hash_sum = r.hash_sum;
     out->omega = r.omega;
@@ -469,7 +484,7 @@ int read_results(mce_graph_s* h, uint64_t first, uint64_t last, mce_result_t* re
     if (ctl_out) *ctl_out = *ctl;
     for (uint32_t i = 0; i < h->num_graphs; i++) {
         if (h->desc[i].n == 0) fill_empty_graph(first, last, &res[i]);
-        else fill_result(h, i, r[i], hist, &res[i]);
+        else fill_result(h, i, r[i], hist, first == 0 && last > 0, &res[i]);
     }
     return MCE_OK;
 }
@@ -540,14 +555,24 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         HIP_TRY(hipStreamSynchronize(s));
         QueueCtl ctl;
         read_results(g, first, last, res, &ctl);
+        if (ctl.error & kErrWatchdog) {
+            // report where the wavefronts were when the deadline passed
+            std::vector<uint32_t> st(c.blocks * c.wpb);
+            uint32_t n[5] = {0, 0, 0, 0, 0};
+            if (hipMemcpy(st.data(), g->d_state.p, 4ull * st.size(), hipMemcpyDeviceToHost) == hipSuccess)
+                for (uint32_t x : st) n[x < 5 ? x : 0]++;
+            std::fprintf(stderr,
+                         "libmce: search stopped by the watchdog (error bits %u); wavefronts: %u idle, "
+                         "%u fetching, %u busy, %u exited, %u never started; work %u hungry %u queue %u\n",
+                         ctl.error, n[kWaveIdle], n[kWaveFetch], n[kWaveBusy], n[kWaveExited], n[0], ctl.work,
+                         (uint32_t)ctl.board, ctl.tail - ctl.head);
+            return MCE_E_DEVICE;
+        }
         if (ctl.error & kErrSpill) {
             floor = c.blocks * c.wpb; // one chunk for every wavefront
             continue;
         }
-        if (ctl.error) {
-            if (ctl.error & kErrWatchdog) std::fprintf(stderr, "libmce: search stopped by the watchdog\n");
-            return MCE_E_DEVICE;
-        }
+        if (ctl.error) return MCE_E_DEVICE;
         if (ctl_out) *ctl_out = ctl;
         float ms = 0.f;
         mce_stats_t st;
@@ -560,7 +585,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         st.blocks = c.blocks;
         st.waves_per_block = c.wpb;
         st.lds_depth = c.lds_depth;
-        st.lds_bytes_per_block = c.wave_lds_words * 4u * c.wpb;
+        st.lds_bytes_per_block = search_lds_bytes(c.wave_lds_words, kRecHeader + 4 * c.w32cap, c.wpb);
         st.donations = ctl.donations;
         st.units = ctl.units;
         st.spills = ctl.spill_levels_written;
@@ -637,6 +662,10 @@ int mce_set_option(int key, int64_t value)
         if (value < 0 || value > 2) return MCE_E_INVAL;
         g_opt.graph = value;
         return MCE_OK;
+    case MCE_OPT_REFRESH_CHILDREN:
+        if (value < 0 || value > (1 << 30)) return MCE_E_INVAL;
+        g_opt.refresh_children = value;
+        return MCE_OK;
     default: return MCE_E_INVAL;
     }
 }
@@ -654,6 +683,7 @@ int mce_get_option(int key, int64_t* value)
     case MCE_OPT_QUEUE_CAP: *value = g_opt.queue_cap; return MCE_OK;
     case MCE_OPT_WATCHDOG_MS: *value = g_opt.watchdog_ms; return MCE_OK;
     case MCE_OPT_GRAPH: *value = g_opt.graph; return MCE_OK;
+    case MCE_OPT_REFRESH_CHILDREN: *value = g_opt.refresh_children; return MCE_OK;
     default: return MCE_E_INVAL;
     }
 }

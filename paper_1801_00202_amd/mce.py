@@ -37,10 +37,11 @@ OPTIONS = {
     "queue_cap": 6,
     "watchdog_ms": 7,
     "graph": 8,
+    "refresh_children": 9,
 }
 DEFAULTS = {
     "waves_per_block": 0, "blocks": 0, "lds_depth": -1, "split_threshold": 0,
-    "check_interval": 0, "queue_cap": 0, "watchdog_ms": 0, "graph": 1,
+    "check_interval": 0, "queue_cap": 0, "watchdog_ms": 0, "graph": 1, "refresh_children": 0,
 }
 
 
