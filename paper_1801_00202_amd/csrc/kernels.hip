@@ -409,30 +409,24 @@ __global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist
     for (uint64_t i = tid; i < hist_total; i += stride) sp.hist[i] = 0ull;
     for (uint64_t i = tid; i < cap; i += stride) sp.seq[i] = (unsigned int)i;
     if (tid < sizeof(QueueCtl) / 8) reinterpret_cast<unsigned long long*>(sp.ctl)[tid] = 0ull;
-    (void)workgroups; // set by the root kernel, after this kernel has cleared the block
+    (void)workgroups;
 }
 
 // Root of each graph (R = {}, P = V, X = {}): its pivot is the first vertex
-// of P (position 0), so L0 = {0} u (V \ N(0)).  The children with branch index
-// in [first, last) become one unit: P = V minus the earlier children, X = the
-// earlier children, L = the selected children.  The root node counts iff
-// first == 0.  One wavefront per graph.
+// of P (position 0), so L0 = {0} u (V \ N(0)).  The root children with branch
+// index in [first, last) are dealt out as units of consecutive children: a
+// unit covering the children of index [a, b) has P = V minus the children
+// before a, X = the children before a, L = the children in [a, b).  The root
+// node counts iff first == 0.
+
+// L0 of graph g, its size, and per-lane ranks (one wavefront).
 template <int WPL>
-__global__ void __launch_bounds__(64) root_kernel(SearchParams sp, uint64_t first, uint64_t last,
-                                                  uint32_t workgroups)
+__device__ __forceinline__ uint32_t root_candidates(const SearchParams& sp, const GraphDesc& gd, uint32_t lane,
+                                                    uint32_t (&V)[WPL], uint32_t (&L0)[WPL],
+                                                    uint32_t (&cnt)[WPL], uint32_t (&incl)[WPL])
 {
-    const uint32_t g = blockIdx.x;
-    // every workgroup of the search starts out waiting for work
-    if (g == 0 && threadIdx.x == 0)
-        __hip_atomic_fetch_add(&sp.ctl->board, (unsigned long long)workgroups, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    const GraphDesc gd = sp.graphs[g];
-    const uint32_t n = gd.n;
-    if (n == 0) return;
-    const uint32_t lane = lane_id();
-    const uint32_t W = gd.w32;
+    const uint32_t n = gd.n, W = gd.w32;
     const uint32_t* row0 = sp.adj + gd.adj_off;
-    uint32_t V[WPL], L0[WPL], cnt[WPL], incl[WPL];
 #pragma unroll
     for (int c = 0; c < WPL; c++) {
         const uint32_t w = (uint32_t)c * 64u + lane;
@@ -441,28 +435,80 @@ __global__ void __launch_bounds__(64) root_kernel(SearchParams sp, uint64_t firs
         V[c] = full;
         L0[c] = full & ~((w < W) ? row0[w] : 0u);
     }
-    const uint32_t total = popc_scan<WPL>(L0, cnt, incl);
-    if (lane == 0) {
-        sp.results[g].root_branches = total;
-        if (first == 0 && last > 0) atomicAdd(&sp.results[g].nodes, 1ull);
+    return popc_scan<WPL>(L0, cnt, incl);
+}
+
+// One wavefront per graph: count the root's children, record the root node,
+// and reserve the queue slots of the graph's units (at most max_units).  The
+// queue is empty and no search runs yet, so slots are taken with a plain add.
+template <int WPL>
+__global__ void __launch_bounds__(64) root_plan_kernel(SearchParams sp, uint64_t first, uint64_t last,
+                                                       uint32_t max_units)
+{
+    const uint32_t g = blockIdx.x;
+    const GraphDesc gd = sp.graphs[g];
+    const uint32_t lane = lane_id();
+    uint32_t total = 0;
+    if (gd.n != 0) {
+        uint32_t V[WPL], L0[WPL], cnt[WPL], incl[WPL];
+        total = root_candidates<WPL>(sp, gd, lane, V, L0, cnt, incl);
     }
+    if (lane != 0) return;
+    DevResult* r = sp.results + g;
+    r->root_branches = total;
+    if (gd.n != 0 && first == 0 && last > 0) atomicAdd(&r->nodes, 1ull);
     const uint32_t lo = first < (uint64_t)total ? (uint32_t)first : total;
     const uint32_t hi = last < (uint64_t)total ? (uint32_t)last : total;
-    if (lo >= hi) return;
-    uint32_t Rb[WPL], P[WPL], X[WPL], L[WPL];
-#pragma unroll
-    for (int c = 0; c < WPL; c++) {
-        const uint32_t before = incl[c] - cnt[c];
-        const uint32_t nb = rank_take(lo, before, cnt[c]);
-        const uint32_t nh = rank_take(hi, before, cnt[c]);
-        const uint32_t lb = low_bits(L0[c], nb);
-        const uint32_t lh = low_bits(L0[c], nh);
-        Rb[c] = 0;
-        X[c] = lb;
-        P[c] = V[c] & ~lb;
-        L[c] = lh & ~lb;
+    uint32_t units = hi > lo ? hi - lo : 0u;
+    if (units > max_units) units = max_units;
+    uint32_t base = 0;
+    if (units != 0) {
+        base = atomicAdd(&sp.ctl->tail, units);
+        atomicAdd(&sp.ctl->work, units);
+        atomicAdd(&sp.ctl->board, (unsigned long long)units << 32);
     }
-    q_push<WPL>(sp, lane, g, W, Rb, P, X, L);
+    r->unit_base = base;
+    r->unit_count = units;
+}
+
+// Grid (graphs, k): wavefront y of graph g writes units y, y + k, ... of the
+// graph into the slots reserved by root_plan_kernel and publishes them.
+template <int WPL>
+__global__ void __launch_bounds__(64) root_units_kernel(SearchParams sp, uint64_t first, uint64_t last)
+{
+    const uint32_t g = blockIdx.x;
+    const uint32_t units = sp.results[g].unit_count;
+    if (blockIdx.y >= units) return;
+    const uint32_t base = sp.results[g].unit_base;
+    const GraphDesc gd = sp.graphs[g];
+    const uint32_t lane = lane_id();
+    const uint32_t W = gd.w32, cs = sp.w32cap;
+    uint32_t V[WPL], L0[WPL], cnt[WPL], incl[WPL];
+    const uint32_t total = root_candidates<WPL>(sp, gd, lane, V, L0, cnt, incl);
+    const uint32_t lo = first < (uint64_t)total ? (uint32_t)first : total;
+    const uint32_t hi = last < (uint64_t)total ? (uint32_t)last : total;
+    const uint64_t m = hi - lo;
+    for (uint32_t j = blockIdx.y; j < units; j += gridDim.y) {
+        const uint32_t a = lo + (uint32_t)(m * j / units);
+        const uint32_t b = lo + (uint32_t)(m * (j + 1) / units);
+        const uint32_t pos = base + j;
+        uint32_t* rec = sp.rec + (size_t)(pos & sp.cap_mask) * sp.rec_words;
+        if (lane == 0) rec[0] = g;
+#pragma unroll
+        for (int c = 0; c < WPL; c++) {
+            const uint32_t before = incl[c] - cnt[c];
+            const uint32_t la = low_bits(L0[c], rank_take(a, before, cnt[c]));
+            const uint32_t lb = low_bits(L0[c], rank_take(b, before, cnt[c]));
+            const uint32_t w = (uint32_t)c * 64u + lane;
+            if (w < W) {
+                rec[kRecHeader + w] = 0u;               // R
+                rec[kRecHeader + cs + w] = V[c] & ~la;  // P
+                rec[kRecHeader + 2 * cs + w] = la;      // X
+                rec[kRecHeader + 3 * cs + w] = lb & ~la; // L
+            }
+        }
+        if (lane == 0) sp.seq[pos & sp.cap_mask] = pos + 1u;
+    }
 }
 
 // ------------------------------------------------------ the search -------
@@ -490,7 +536,8 @@ struct WgHdr {
     uint32_t done;      // stop: search over or aborted
     uint32_t snap;      // global donations still wanted (snapshot)
     uint32_t ticks;     // children processed by the workgroup, in steps of check_interval
-    uint32_t pad[8];
+    uint32_t hungry;    // the workgroup is counted as waiting in the low half of ctl->board
+    uint32_t pad[7];
 };
 static_assert(sizeof(WgHdr) == kWgHdrWords * 4, "header size");
 
@@ -916,8 +963,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 const uint32_t n0 = bcast0(lds_ld(&hdr->lq_n));
                 const uint32_t dn0 = bcast0(lds_ld(&hdr->done));
                 const uint32_t f0 = bcast0(lds_ld(&hdr->fetcher));
-                const uint32_t b0 = bcast0(lds_ld(&hdr->busy));
-                if (n0 == 0u && dn0 == 0u && (f0 != 0u || b0 != 0u)) {
+                if (n0 == 0u && dn0 == 0u && f0 != 0u) { // a sibling fetches for the workgroup
                     if ((++idle_iters & 255u) == 0u && overdue()) {
                         give_up();
                         stop = true;
@@ -947,7 +993,12 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 stop = true;
                 break;
             }
-            uint32_t fetch = 0, went_inactive = 0;
+            // This wavefront is idle and the LIFO is empty: it fetches for the
+            // workgroup unless a sibling already does.  The workgroup is then
+            // counted as waiting on the board (once, until it gets a unit
+            // from HBM), and leaves ctl->work if none of its wavefronts holds
+            // a unit any more.
+            uint32_t fetch = 0, went_inactive = 0, reg = 0, inactive = 0;
             if (lane == 0 && lds_ld(&hdr->fetcher) == 0u) {
                 lds_st(&hdr->fetcher, 1u);
                 fetch = 1;
@@ -955,13 +1006,19 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                     lds_st(&hdr->active, 0u);
                     went_inactive = 1;
                 }
-                if (lds_ld(&hdr->active) != 0u) fetch = 2; // siblings still busy: wait locally
+                inactive = lds_ld(&hdr->active) == 0u;
+                if (lds_ld(&hdr->hungry) == 0u) {
+                    lds_st(&hdr->hungry, 1u);
+                    reg = 1;
+                }
             }
             wg_unlock(hdr, lane);
             fetch = bcast0(fetch);
-            if (bcast0(went_inactive) && lane == 0) {
-                __hip_atomic_fetch_add(&sp.ctl->board, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            inactive = bcast0(inactive);
+            if (lane == 0) {
+                if (reg) __hip_atomic_fetch_add(&sp.ctl->board, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (went_inactive)
+                    __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (fetch == 1) {
                 set_state(kWaveFetch);
@@ -986,22 +1043,22 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                         lds_st(&hdr->active, 1u);
                         lds_st(&hdr->busy, lds_ld(&hdr->busy) + 1);
                         lds_st(&hdr->fetcher, 0u);
+                        lds_st(&hdr->hungry, 0u); // set by this or an earlier fetcher
                     }
                     wg_unlock(hdr, lane);
                     if (lane == 0) {
-                        if (was_active) { // the unit's count is already covered by this workgroup
+                        // one unit fewer in the queue, one waiting workgroup fewer
+                        __hip_atomic_fetch_sub(&sp.ctl->board, (1ull << 32) + 1ull, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        // the unit's count is already covered by this workgroup
+                        if (was_active)
                             __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_fetch_sub(&sp.ctl->board, 1ull << 32, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                        } else {
-                            __hip_atomic_fetch_sub(&sp.ctl->board, (1ull << 32) + 1ull, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                        }
                     }
                     src = 2;
                     break;
                 }
-                if ((polls & 1u) == 0u) {
+                if (inactive && (polls & 1u) == 0u) {
+                    // only a workgroup that holds no work can see the end
                     polls++;
                     uint32_t w = 0, e = 0;
                     if (lane == 0) {
@@ -1023,8 +1080,6 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 } else if (lane == 0) {
                     lds_st(&hdr->fetcher, 0u);
                 }
-            } else if (fetch == 2 && lane == 0) {
-                lds_st(&hdr->fetcher, 0u);
             }
             for (uint32_t i = 0; i < backoff; i++) __builtin_amdgcn_s_sleep(8);
             if (backoff < 8) backoff <<= 1;
@@ -1363,12 +1418,18 @@ hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hi
 }
 
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
-                       uint64_t first, uint64_t last, uint32_t workgroups, hipStream_t s)
+                       uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s)
 {
-    if (max_w32 <= 64)
-        hipLaunchKernelGGL(root_kernel<1>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, workgroups);
-    else
-        hipLaunchKernelGGL(root_kernel<2>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, workgroups);
+    // writers per graph: enough to fill the queue quickly, few per graph in a batch
+    uint32_t k = 1;
+    while (k < 64 && k < max_units && (uint64_t)num_graphs * k < 4096) k <<= 1;
+    if (max_w32 <= 64) {
+        hipLaunchKernelGGL(root_plan_kernel<1>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
+        hipLaunchKernelGGL(root_units_kernel<1>, dim3(num_graphs, k), dim3(64), 0, s, sp, first, last);
+    } else {
+        hipLaunchKernelGGL(root_plan_kernel<2>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
+        hipLaunchKernelGGL(root_units_kernel<2>, dim3(num_graphs, k), dim3(64), 0, s, sp, first, last);
+    }
     return hipGetLastError();
 }
 

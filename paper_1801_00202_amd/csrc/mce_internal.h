@@ -42,6 +42,7 @@ struct DevResult {
     unsigned long long count, nodes, children, dead_ends, hash_xor, hash_sum;
     unsigned long long root_branches;
     unsigned int omega, status;
+    unsigned int unit_base, unit_count; // queue slots of the graph's root units
 };
 
 // Control block of one search launch.  The words every workgroup polls sit
@@ -113,7 +114,7 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
                         uint32_t cap, uint32_t workgroups, hipStream_t s);
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
-                       uint64_t first, uint64_t last, uint32_t workgroups, hipStream_t s);
+                       uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s);
 hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s);
 hipError_t search_occupancy(uint32_t max_w32, uint32_t waves_per_block, uint32_t lds_bytes,

@@ -424,7 +424,9 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
                   uint64_t last, hipStream_t s, bool timed)
 {
     HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.cap, c.blocks, s));
-    HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, c.blocks, s));
+    // the root children fill at most half of the queue; donations use the rest
+    const uint32_t max_units = std::max<uint32_t>(1u, (c.cap / 2u) / h->num_graphs);
+    HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, max_units, s));
     std::memcpy(h->h_params.p, &sp, sizeof(sp));
     HIP_TRY(hipMemcpyAsync(h->d_params.p, h->h_params.p, sizeof(sp), hipMemcpyHostToDevice, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));

@@ -1,0 +1,393 @@
+"""Pins of the CPU oracle to facts fixed outside it (CPU only).
+
+What pins what:
+  * the report hash: the published SplitMix64 outputs for seed 0, and the
+    Moon-Moser graph, whose maximal cliques are exactly the transversals of its
+    triangles (enumerated here without any search);
+  * the clique set, count, histogram and omega: closed forms (complete,
+    empty, cycles, paths, stars, complete multipartite, Moon-Moser, disjoint
+    unions), relabelling invariance, and agreement of three different
+    algorithms (subset brute force, Tomita pivot, GreedyBB) on every graph with
+    at most 6 vertices and on seeded G(n, p) up to 20 vertices;
+  * the node count (the paper's "steps"): closed forms for complete, empty,
+    Moon-Moser and equal-part multipartite graphs, the subproblem of the
+    worked example (Sec. 5) and the GreedyBB / TomitaBB columns of Table 1;
+  * the ordering: hand cases where the degree taken in the remaining graph
+    and the static degree give different orders (Sec. 4.2), and the argmax
+    property on seeded graphs;
+  * the expected number of maximal cliques of G(n, p) (first moment).
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+M64 = (1 << 64) - 1
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+
+
+def _adj_from_edges(n, edges):
+    return synth.edge_list_to_rows(n, edges)
+
+
+def _same_report(a, b):
+    for k in ("count", "hist", "hash_xor", "hash_sum", "omega"):
+        assert a[k] == b[k], (k, a[k], b[k])
+
+
+# ------------------------------------------------------------------ hash ---
+
+def test_mix64_is_splitmix64(orc):
+    # SplitMix64 (Steele, Lea & Flood 2014) seeded with 0 adds the golden
+    # gamma to its state before each output; its first outputs are published.
+    expect = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    got = [orc.mix64((GOLDEN_GAMMA * i) & M64) for i in range(1, 5)]
+    assert got == expect
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_moon_moser_transversals(orc, k):
+    """Complement of k disjoint triangles: the maximal cliques are exactly the
+    3^k transversals (one vertex from each triangle).  Enumerated directly
+    here, then hashed clique by clique, and compared with the search."""
+    rows = synth.moon_moser(k)
+    cl = [tuple(3 * t + c for t, c in enumerate(choice)) for choice in itertools.product(range(3), repeat=k)]
+    hx, hs = 0, 0
+    for c in cl:
+        h = orc.clique_hash(sorted(c))
+        hx ^= h
+        hs = (hs + h) & M64
+    for fn in (orc.greedy, orc.tomita):
+        r = fn(rows)
+        assert r["count"] == 3 ** k
+        assert r["hist"][k] == 3 ** k and sum(r["hist"]) == 3 ** k
+        assert r["omega"] == k
+        assert (r["hash_xor"], r["hash_sum"]) == (hx, hs)
+    res, lst = orc.greedy_list(rows)
+    assert sorted(lst) == sorted(cl)
+
+
+def test_moon_moser_relabelled(orc):
+    """Hashes are taken on sorted input ids: a relabelled copy hashes its own
+    transversals."""
+    k = 5
+    perm = np.random.Generator(np.random.PCG64(7)).permutation(3 * k)
+    rows = synth.relabel(synth.moon_moser(k), perm)
+    hx, hs = 0, 0
+    for choice in itertools.product(range(3), repeat=k):
+        c = sorted(int(perm[3 * t + ch]) for t, ch in enumerate(choice))
+        h = orc.clique_hash(c)
+        hx ^= h
+        hs = (hs + h) & M64
+    r = orc.greedy(rows)
+    assert (r["count"], r["hash_xor"], r["hash_sum"]) == (3 ** k, hx, hs)
+
+
+def test_hash_order_and_size_sensitive(orc):
+    # the hash is a function of the sorted set: it separates sets that a
+    # plain xor or sum of ids would not
+    assert orc.clique_hash([0, 3]) != orc.clique_hash([1, 2])
+    assert orc.clique_hash([]) != orc.clique_hash([0])
+    assert orc.clique_hash([5]) != orc.clique_hash([5, 5])
+
+
+# --------------------------------------------------------- closed forms ---
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 65, 200])
+def test_complete(orc, n):
+    r = orc.greedy(synth.complete(n))
+    assert r["count"] == 1 and r["hist"][n] == 1 and r["omega"] == n
+    # one node per level: the root, then a chain of n - 1 nodes
+    assert r["nodes"] == n and r["children"] == n and r["dead_ends"] == 0
+    assert orc.tomita(synth.complete(n))["nodes"] == n
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 100])
+def test_empty(orc, n):
+    r = orc.greedy(synth.empty(n))
+    assert r["count"] == n and r["hist"][1] == n and r["omega"] == 1
+    assert r["nodes"] == 1 and r["children"] == n and r["dead_ends"] == 0
+
+
+def test_zero_vertices(orc):
+    # M(G) = {empty set}: one clique of size 0, no node
+    r = orc.greedy(np.zeros((0, 1), dtype=np.uint64))
+    assert r["count"] == 1 and r["hist"] == [1] and r["nodes"] == 0 and r["omega"] == 0
+    assert r["hash_xor"] == orc.clique_hash([]) == orc.mix64(0)
+    assert orc.brute(np.zeros((0, 1), dtype=np.uint64))["count"] == 1
+
+
+@pytest.mark.parametrize("n", [4, 5, 9, 64, 129])
+def test_cycle(orc, n):
+    r = orc.greedy(synth.cycle(n))
+    assert r["count"] == n and r["hist"][2] == n and r["omega"] == 2
+
+
+def test_triangle_is_complete(orc):
+    assert orc.greedy(synth.cycle(3))["count"] == 1
+
+
+@pytest.mark.parametrize("n", [2, 3, 10, 100])
+def test_path(orc, n):
+    r = orc.greedy(synth.path(n))
+    assert r["count"] == n - 1 and r["hist"][2] == n - 1
+
+
+@pytest.mark.parametrize("leaves", [1, 2, 7, 80])
+def test_star(orc, leaves):
+    r = orc.greedy(synth.star(leaves + 1))  # centre 0 and the leaves
+    assert r["count"] == leaves and r["hist"][2] == leaves
+
+
+@pytest.mark.parametrize("parts", [(1, 1), (2, 3), (3, 3, 3), (4, 1, 2, 5), (2,) * 10, (5,) * 4, (3,) * 6])
+def test_complete_multipartite(orc, parts):
+    rows = synth.complete_multipartite(parts)
+    k = len(parts)
+    prod = math.prod(parts)
+    r = orc.greedy(rows)
+    assert r["count"] == prod and r["hist"][k] == prod and r["omega"] == k
+    if len(set(parts)) == 1 and parts[0] > 1:
+        a = parts[0]
+        # each node branches on every vertex of its first part; the tree is
+        # full a-ary of depth k - 1 over the nodes
+        assert r["nodes"] == (a ** k - 1) // (a - 1)
+    assert orc.tomita(rows)["count"] == prod
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 10])
+def test_moon_moser_nodes(orc, k):
+    r = orc.greedy(synth.moon_moser(k))
+    assert r["count"] == 3 ** k
+    assert r["nodes"] == (3 ** k - 1) // 2
+
+
+def test_disjoint_union(orc):
+    parts = [synth.gnp(12, 0.5, 1), synth.complete(5), synth.cycle(7), synth.gnp(15, 0.3, 2)]
+    rows = synth.disjoint_union(*parts)
+    r = orc.greedy(rows)
+    hist = np.zeros(20, dtype=np.int64)
+    total = 0
+    for g in parts:
+        rg = orc.greedy(g)
+        total += rg["count"]
+        hist[: len(rg["hist"])] += np.array(rg["hist"], dtype=np.int64)
+    # the clique multisets of the components add
+    assert r["count"] == total
+    h = np.array(r["hist"] + [0] * (20 - len(r["hist"])), dtype=np.int64)
+    assert (h == hist).all()
+    # and the listed cliques are the components' cliques, shifted
+    _, lst = orc.greedy_list(rows)
+    want, off = [], 0
+    for g in parts:
+        _, lg = orc.greedy_list(g)
+        want += [tuple(v + off for v in c) for c in lg]
+        off += g.shape[0]
+    assert sorted(lst) == sorted(want)
+
+
+# ------------------------------------------------- exhaustive and seeded ---
+
+def _all_graphs(n):
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    for mask in range(1 << len(pairs)):
+        adj = np.zeros((n, n), dtype=bool)
+        for b, (i, j) in enumerate(pairs):
+            if mask >> b & 1:
+                adj[i, j] = adj[j, i] = True
+        yield synth.pack_rows(adj)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_all_small_graphs(orc, n):
+    for rows in _all_graphs(n):
+        b = orc.brute(rows)
+        _same_report(orc.greedy(rows), b)
+        _same_report(orc.tomita(rows), b)
+
+
+def test_all_graphs_on_six_vertices(orc):
+    seen = 0
+    for rows in _all_graphs(6):
+        b = orc.brute(rows)
+        _same_report(orc.greedy(rows), b)
+        seen += 1
+    assert seen == 1 << 15
+
+
+@pytest.mark.parametrize("n", [8, 13, 20])
+@pytest.mark.parametrize("p", [0.1, 0.3, 0.5, 0.7, 0.9])
+def test_seeded_gnp_vs_brute(orc, n, p):
+    for seed in range(2):
+        rows = synth.gnp(n, p, seed)
+        b = orc.brute(rows)
+        _same_report(orc.greedy(rows), b)
+        _same_report(orc.tomita(rows), b)
+
+
+@pytest.mark.parametrize("n,p", [(40, 0.5), (70, 0.3), (25, 0.8)])
+def test_relabelling_invariance(orc, n, p):
+    rows = synth.gnp(n, p, 3)
+    perm = np.random.Generator(np.random.PCG64(11)).permutation(n)
+    r0, l0 = orc.greedy_list(rows)
+    r1, l1 = orc.greedy_list(synth.relabel(rows, perm))
+    assert r0["count"] == r1["count"] and r0["hist"] == r1["hist"]
+    assert sorted(tuple(sorted(int(perm[v]) for v in c)) for c in l0) == sorted(l1)
+
+
+def test_list_matches_totals(orc):
+    rows = synth.gnp(60, 0.5, 4)
+    r, lst = orc.greedy_list(rows)
+    assert len(lst) == r["count"] == len(set(lst))
+    hx = 0
+    for c in lst:
+        assert list(c) == sorted(c)
+        hx ^= orc.clique_hash(c)
+    assert hx == r["hash_xor"]
+    adj = synth.unpack_rows(rows)
+    for c in lst[:200]:
+        # a clique, and maximal
+        for u, v in itertools.combinations(c, 2):
+            assert adj[u, v]
+        common = np.ones(60, dtype=bool)
+        for v in c:
+            common &= adj[v]
+        assert not common.any()
+
+
+def test_range_partition(orc):
+    """The root's children split into ranges add up to the whole search."""
+    rows = synth.gnp(80, 0.5, 5)
+    full = orc.greedy(rows)
+    nb = orc.root_branches(rows)
+    cuts = [0, 1, 7, nb // 2, nb - 1, nb]
+    tot = {"count": 0, "nodes": 0, "children": 0, "dead_ends": 0, "hash_xor": 0, "hash_sum": 0}
+    for a, b in zip(cuts, cuts[1:]):
+        r = orc.greedy_range(rows, a, b)
+        for k in tot:
+            tot[k] = (tot[k] ^ r[k]) if k == "hash_xor" else (tot[k] + r[k]) & M64
+    for k in tot:
+        assert tot[k] == full[k], k
+
+
+def test_multithreaded_oracle_agrees(orc):
+    rows = synth.gnp(150, 0.5, 6)
+    a, b = orc.greedy(rows), orc.greedy(rows, threads=4)
+    assert a == b
+
+
+# ---------------------------------------------------------------- order ---
+
+def test_order_hand_cases(orc):
+    # star: the centre (vertex 0) has the largest degree
+    assert orc.order(synth.star(6))[0] == 0
+    # path 0-1-2-3-4: degrees 1,2,2,2,1.  Taking degrees in the remaining
+    # graph gives 1 (tie with 2 and 3 goes to the smaller id), then 3 (degree
+    # 2 once 1 is gone), then 0, 2, 4 (all isolated).  Static degrees would
+    # give 1, 2, 3, 0, 4.
+    assert list(orc.order(synth.path(5))) == [1, 3, 0, 2, 4]
+    # two stars whose centres 0 and 4 are joined
+    rows = _adj_from_edges(7, [(0, 1), (0, 2), (0, 3), (4, 5), (4, 6), (0, 4)])
+    assert list(orc.order(rows)) == [0, 4, 1, 2, 3, 5, 6]
+    # ties everywhere: the identity
+    assert list(orc.order(synth.complete(9))) == list(range(9))
+    assert list(orc.order(synth.empty(9))) == list(range(9))
+
+
+@pytest.mark.parametrize("n,p,seed", [(50, 0.3, 0), (120, 0.6, 1), (200, 0.1, 2)])
+def test_order_is_dynamic_argmax(orc, n, p, seed):
+    rows = synth.gnp(n, p, seed)
+    adj = synth.unpack_rows(rows).astype(np.int64)
+    order = orc.order(rows)
+    assert sorted(order.tolist()) == list(range(n))
+    alive = np.ones(n, dtype=bool)
+    for v in order:
+        deg = adj[:, alive].sum(axis=1)
+        deg[~alive] = -1
+        best = deg.max()
+        assert deg[v] == best and v == int(np.flatnonzero(deg == best)[0])
+        alive[v] = False
+
+
+# ------------------------------------------------------- worked example ---
+
+def _worked_example():
+    with open(os.path.join(GOLDEN, "worked_example.json")) as f:
+        ex = json.load(f)
+    labels = ex["ordering_labels"]
+    pos = {lab: i for i, lab in enumerate(labels)}
+    n = len(labels)
+    edges = [(pos[9], pos[v]) for v in ex["P"]] + [(pos[a], pos[b]) for a, b in ex["edges_in_P"]]
+    rows = _adj_from_edges(n, edges)
+    return ex, pos, rows
+
+
+def test_worked_example_subproblem(orc):
+    """Sec. 5: inside N(9) GreedyBB pivots on 8 and TomitaBB on 6; GreedyBB
+    needs one node fewer in 9's subtree."""
+    ex, pos, rows = _worked_example()
+    adj = synth.unpack_rows(rows)
+    P = [pos[v] for v in ex["P"]]
+    for v, d in ex["degrees_in_P"].items():
+        assert sum(adj[pos[int(v)], q] for q in P) == d
+    R = [pos[v] for v in ex["R"]]
+    g = orc.subproblem(rows, R, P, [], "greedy")
+    t = orc.subproblem(rows, R, P, [], "tomita")
+    assert g["nodes"] == ex["greedy_nodes_in_subtree"]
+    assert t["nodes"] == ex["tomita_nodes_in_subtree"]
+    inv = {i: lab for lab, i in pos.items()}
+    want = sorted(tuple(sorted(pos[v] for v in c)) for c in ex["cliques_in_subtree"])
+    assert g["count"] == t["count"] == len(want)
+    # the subproblem reports R plus its extension: compare the hash of the
+    # listed cliques (labels = positions here)
+    hx = 0
+    for c in want:
+        hx ^= orc.clique_hash(list(c))
+    assert g["hash_xor"] == t["hash_xor"] == hx
+    # branch sets printed in the text
+    p_g = pos[ex["greedy_pivot"]]
+    assert sorted(inv[q] for q in P if not adj[p_g, q]) == sorted(ex["greedy_branch_set"])
+    p_t = pos[ex["tomita_pivot"]]
+    assert sorted(inv[q] for q in P if not adj[p_t, q]) == sorted(ex["tomita_branch_set"])
+
+
+# ---------------------------------------------------------- statistics ---
+
+def test_expected_mu_matches_seeded_graphs(orc):
+    """E[mu(G(n,p))] by the first moment vs the mean over seeded graphs."""
+    for n, p, seeds in [(30, 0.5, 120), (60, 0.3, 60)]:
+        mus = np.array([orc.greedy(synth.gnp(n, p, s))["count"] for s in range(seeds)], dtype=np.float64)
+        se = mus.std(ddof=1) / math.sqrt(seeds)
+        assert abs(mus.mean() - synth.expected_mu(n, p)) < 4.0 * se + 1e-9, (n, p, mus.mean(), synth.expected_mu(n, p))
+
+
+def test_expected_mu_against_table1():
+    """The first moment reproduces the paper's mu column (Table 1) to a few %."""
+    with open(os.path.join(GOLDEN, "table1_random.json")) as f:
+        rows = json.load(f)["rows"]
+    for r in rows:
+        e = synth.expected_mu(r["n"], r["p"])
+        assert abs(e / r["mu"] - 1.0) < 0.1, (r, e)
+
+
+def test_table1_step_calibration(orc):
+    """Nodes per maximal clique of GreedyBB and TomitaBB over 5 seeds vs the
+    steps per clique of Table 1 (the paper's graphs and seeds are unknown, so
+    per-clique ratios are compared)."""
+    with open(os.path.join(GOLDEN, "table1_random.json")) as f:
+        rows = json.load(f)["rows"]
+    for r in rows:
+        if r["mu"] > 1e6:
+            continue
+        g = [orc.greedy(synth.gnp(r["n"], r["p"], s)) for s in range(5)]
+        t = [orc.tomita(synth.gnp(r["n"], r["p"], s)) for s in range(5)]
+        mu = np.mean([x["count"] for x in g])
+        gb = np.mean([x["nodes"] for x in g]) / mu
+        tb = np.mean([x["nodes"] for x in t]) / mu
+        assert abs(gb / (r["greedybb_steps"] / r["mu"]) - 1.0) < 0.05, (r, gb)
+        assert abs(tb / (r["tomitabb_steps"] / r["mu"]) - 1.0) < 0.08, (r, tb)
