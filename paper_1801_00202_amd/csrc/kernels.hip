@@ -186,19 +186,14 @@ __device__ __forceinline__ uint32_t popc_scan(const uint32_t (&s)[WPL], uint32_t
     return base;
 }
 
-// ---------------------------------------------------------------- queue ---
-//
-// Bounded MPMC queue (one sequence number per slot, after D. Vyukov).  Slot
-// seq == pos: free for the producer of ticket pos; seq == pos + 1: holds the
-// unit of ticket pos.  Lane 0 runs the protocol; the wavefront moves the data.
+// ------------------------------------------------ words shared in HBM ---
 //
 // Coherence across the XCDs' separate L2 caches: every word that crosses
-// wavefronts (records, sequence numbers, counters) is read and written with
+// workgroups (records, mailboxes, counters) is read and written with
 // device-scope accesses (sc1), which bypass the non-coherent cache levels, and
-// a wait for all outstanding vector memory operations (vmcnt(0)) separates the
-// record from the sequence number that publishes or frees it.  No L2
-// write-back or invalidate is ever issued, so the adjacency rows cached in L2
-// stay put.
+// a wait for all outstanding vector memory operations (vmcnt(0)) separates a
+// record from the word that publishes it.  No L2 write-back or invalidate is
+// ever issued, so the adjacency rows cached in L2 stay put.
 
 __device__ __forceinline__ uint32_t ld_dev(const uint32_t* p)
 {
@@ -218,71 +213,12 @@ __device__ __forceinline__ void vm_drain()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__device__ __forceinline__ bool q_pop(const SearchParams& sp, uint32_t lane, uint32_t* out)
-{
-    uint32_t pos = 0, ok = 0;
-    if (lane == 0) {
-        unsigned int* head = &sp.ctl->head;
-        pos = ld_dev(head);
-        for (;;) {
-            const uint32_t seq = ld_dev(&sp.seq[pos & sp.cap_mask]);
-            const int32_t dif = (int32_t)(seq - (pos + 1u));
-            if (dif == 0) {
-                if (__hip_atomic_compare_exchange_weak(head, &pos, pos + 1u, __ATOMIC_RELAXED,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 1;
-                    break;
-                }
-            } else if (dif < 0) {
-                break; // empty
-            } else {
-                pos = ld_dev(head);
-            }
-        }
-    }
-    ok = bcast0(ok);
-    *out = bcast0(pos);
-    return ok != 0;
-}
-
-// Hand a slot back to producers once its record has been read.
-__device__ __forceinline__ void q_release_slot(const SearchParams& sp, uint32_t lane, uint32_t pos)
-{
-    vm_drain();
-    if (lane == 0) st_dev(&sp.seq[pos & sp.cap_mask], pos + sp.cap_mask + 1u);
-}
-
+// Copy a unit (R, P, X, L of graph g) into a record in HBM.
 template <int WPL>
-__device__ bool q_push(const SearchParams& sp, uint32_t lane, uint32_t g, uint32_t W,
-                       const uint32_t (&Rb)[WPL], const uint32_t (&P)[WPL],
-                       const uint32_t (&X)[WPL], const uint32_t (&L)[WPL])
+__device__ __forceinline__ void store_record(uint32_t* r, uint32_t cs, uint32_t lane, uint32_t g, uint32_t W,
+                                             const uint32_t (&Rb)[WPL], const uint32_t (&P)[WPL],
+                                             const uint32_t (&X)[WPL], const uint32_t (&L)[WPL])
 {
-    uint32_t pos = 0, ok = 0;
-    if (lane == 0) {
-        unsigned int* tail = &sp.ctl->tail;
-        pos = ld_dev(tail);
-        for (;;) {
-            const uint32_t seq = ld_dev(&sp.seq[pos & sp.cap_mask]);
-            const int32_t dif = (int32_t)(seq - pos);
-            if (dif == 0) {
-                if (__hip_atomic_compare_exchange_weak(tail, &pos, pos + 1u, __ATOMIC_RELAXED,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 1;
-                    break;
-                }
-            } else if (dif < 0) {
-                break; // full
-            } else {
-                pos = ld_dev(tail);
-            }
-        }
-        if (ok) __hip_atomic_fetch_add(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    ok = bcast0(ok);
-    pos = bcast0(pos);
-    if (!ok) return false;
-    uint32_t* r = sp.rec + (size_t)(pos & sp.cap_mask) * sp.rec_words;
-    const uint32_t cs = sp.w32cap;
     if (lane == 0) st_dev(&r[0], g);
 #pragma unroll
     for (int c = 0; c < WPL; c++) {
@@ -294,12 +230,6 @@ __device__ bool q_push(const SearchParams& sp, uint32_t lane, uint32_t g, uint32
             st_dev(&r[kRecHeader + 3 * cs + w], L[c]);
         }
     }
-    vm_drain();
-    if (lane == 0) {
-        st_dev(&sp.seq[pos & sp.cap_mask], pos + 1u);
-        __hip_atomic_fetch_add(&sp.ctl->board, 1ull << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
 }
 
 // ------------------------------------------------------------ kernels ----
@@ -397,9 +327,9 @@ __global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, co
     }
 }
 
-// Zero the per-graph results and the control block; seq[i] = i (all slots free).
-__global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist_total, uint32_t cap,
-                             uint32_t workgroups)
+// Zero the per-graph results, the histograms, the control block and the
+// mailboxes.
+__global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist_total, uint32_t workgroups)
 {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -407,9 +337,10 @@ __global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist
     const uint64_t res_words = (uint64_t)num_graphs * (sizeof(DevResult) / 8);
     for (uint64_t i = tid; i < res_words; i += stride) res[i] = 0ull;
     for (uint64_t i = tid; i < hist_total; i += stride) sp.hist[i] = 0ull;
-    for (uint64_t i = tid; i < cap; i += stride) sp.seq[i] = (unsigned int)i;
+    uint32_t* mail = reinterpret_cast<uint32_t*>(sp.mail);
+    const uint64_t mail_words = (uint64_t)workgroups * (sizeof(Mailbox) / 4);
+    for (uint64_t i = tid; i < mail_words; i += stride) mail[i] = 0u;
     if (tid < sizeof(QueueCtl) / 8) reinterpret_cast<unsigned long long*>(sp.ctl)[tid] = 0ull;
-    (void)workgroups;
 }
 
 // Root of each graph (R = {}, P = V, X = {}): its pivot is the first vertex
@@ -439,8 +370,7 @@ __device__ __forceinline__ uint32_t root_candidates(const SearchParams& sp, cons
 }
 
 // One wavefront per graph: count the root's children, record the root node,
-// and reserve the queue slots of the graph's units (at most max_units).  The
-// queue is empty and no search runs yet, so slots are taken with a plain add.
+// and reserve pool slots for the graph's units (at most max_units).
 template <int WPL>
 __global__ void __launch_bounds__(64) root_plan_kernel(SearchParams sp, uint64_t first, uint64_t last,
                                                        uint32_t max_units)
@@ -463,16 +393,16 @@ __global__ void __launch_bounds__(64) root_plan_kernel(SearchParams sp, uint64_t
     if (units > max_units) units = max_units;
     uint32_t base = 0;
     if (units != 0) {
-        base = atomicAdd(&sp.ctl->tail, units);
+        base = atomicAdd(&sp.ctl->pool_size, units);
         atomicAdd(&sp.ctl->work, units);
-        atomicAdd(&sp.ctl->board, (unsigned long long)units << 32);
     }
     r->unit_base = base;
     r->unit_count = units;
 }
 
 // Grid (graphs, k): wavefront y of graph g writes units y, y + k, ... of the
-// graph into the slots reserved by root_plan_kernel and publishes them.
+// graph into the pool slots reserved by root_plan_kernel.  The search kernel
+// runs after this one, so plain stores suffice.
 template <int WPL>
 __global__ void __launch_bounds__(64) root_units_kernel(SearchParams sp, uint64_t first, uint64_t last)
 {
@@ -492,7 +422,7 @@ __global__ void __launch_bounds__(64) root_units_kernel(SearchParams sp, uint64_
         const uint32_t a = lo + (uint32_t)(m * j / units);
         const uint32_t b = lo + (uint32_t)(m * (j + 1) / units);
         const uint32_t pos = base + j;
-        uint32_t* rec = sp.rec + (size_t)(pos & sp.cap_mask) * sp.rec_words;
+        uint32_t* rec = sp.rec + (size_t)pos * sp.rec_words;
         if (lane == 0) rec[0] = g;
 #pragma unroll
         for (int c = 0; c < WPL; c++) {
@@ -507,39 +437,45 @@ __global__ void __launch_bounds__(64) root_units_kernel(SearchParams sp, uint64_
                 rec[kRecHeader + 3 * cs + w] = lb & ~la; // L
             }
         }
-        if (lane == 0) sp.seq[pos & sp.cap_mask] = pos + 1u;
     }
 }
 
 // ------------------------------------------------------ the search -------
 //
-// Scheduling is two-level, so that the hot path touches no shared HBM word:
+// Scheduling is two-level, so that no HBM word is polled by every workgroup:
 //   * inside a workgroup, wavefronts share a small LIFO of units in LDS.  A
-//     busy wavefront looks at two LDS counters every check_interval children
-//     and, while siblings wait and the LIFO is short, hands over half of the
-//     candidates of its shallowest frame;
-//   * between workgroups, units move through the HBM queue.  Only a workgroup
-//     whose wavefronts are all idle fetches from it, and busy workgroups
-//     publish to it only while the LDS snapshot of the number of hungry
-//     workgroups (refreshed by one wavefront per workgroup every
-//     refresh period) says some are waiting.
-// Termination: ctl->work counts the units in the HBM queue plus the
-// workgroups that hold work (running or in their LDS LIFO); the search is over
-// when it reaches zero.
+//     busy wavefront looks at a few LDS counters every check_interval
+//     children and, while siblings wait and the LIFO is short (or the LIFO is
+//     empty), hands over the later half of the candidates of its shallowest
+//     big-enough frame;
+//   * between workgroups, a workgroup whose wavefronts are out of work first
+//     takes root units from the pool (one atomic counter), then asks other
+//     workgroups, one at a time and chosen at random, through their
+//     mailboxes.  A busy workgroup looks at its own mailbox every
+//     refresh_children children of the workgroup and answers with a unit split
+//     off in the same way, or with a refusal.
+// Termination: ctl->work counts the root units not handed out, the units in
+// transit to a mailbox and the workgroups that hold work (running or in their
+// LIFO); the search is over when it reaches zero.
 
 struct WgHdr {
     uint32_t lock;      // LDS spin lock over the LIFO and the counters below
     uint32_t busy;      // wavefronts holding a unit
     uint32_t lq_n;      // units in the LIFO
     uint32_t active;    // this workgroup is counted in ctl->work
-    uint32_t fetcher;   // a wavefront is fetching from the HBM queue
+    uint32_t fetcher;   // a wavefront is looking for work outside the workgroup
     uint32_t done;      // stop: search over or aborted
-    uint32_t snap;      // global donations still wanted (snapshot)
+    uint32_t req;       // asking workgroup + 1, taken from the mailbox and not answered yet
     uint32_t ticks;     // children processed by the workgroup, in steps of check_interval
-    uint32_t hungry;    // the workgroup is counted as waiting in the low half of ctl->board
-    uint32_t pad[7];
+    uint32_t out;       // workgroup + 1 that this workgroup has asked (0: none,
+                        // kOutReading: the answer is a unit being read)
+    uint32_t pool_left; // root units may be left in the pool
+    uint32_t pool_size; // root units in the pool
+    uint32_t rng;       // xorshift state for choosing whom to ask
+    uint32_t pad[4];
 };
 static_assert(sizeof(WgHdr) == kWgHdrWords * 4, "header size");
+constexpr uint32_t kOutReading = 0xffffffffu;
 
 __device__ __forceinline__ uint32_t lds_ld(uint32_t* p)
 {
@@ -769,11 +705,11 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
     }
 }
 
-// The look at siblings and at the board every check_interval children.  The
+// The look at siblings and at the mailbox every check_interval children.  The
 // current frame is in its LDS slot; frames 0..d-1 are on the stack.  May hand
 // the later half of the candidates of the shallowest big-enough frame to the
-// LDS LIFO or to the HBM queue (the current frame's L in its slot is updated
-// then).  Returns 1 if the search must stop.
+// LDS LIFO or to the workgroup that asked (the current frame's L in its slot
+// is updated then).  Returns 1 if the search must stop.
 template <int WPL>
 __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __restrict__ spp, uint32_t* smem,
                                                          uint32_t* wl, uint32_t d_v, uint32_t W_v, uint32_t g_v,
@@ -799,25 +735,27 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
     if (bcast0(lds_ld(&hdr->done))) return 1;
     const uint32_t busy = bcast0(lds_ld(&hdr->busy));
     const uint32_t lqn = bcast0(lds_ld(&hdr->lq_n));
-    // Where to hand work: first to siblings that wait for it, then to hungry
-    // workgroups, and otherwise keep one unit in stock in the LIFO so that a
-    // wavefront that finishes finds work at once.
+    // Where to hand work: first to siblings that wait for it, then to a
+    // workgroup that asked through the mailbox, and otherwise keep one unit in
+    // stock in the LIFO so that a wavefront that finishes finds work at once.
     const bool siblings_wait = lqn < kLocalSlots && NW - busy > lqn;
     bool to_local = siblings_wait;
-    bool to_global = false;
-    if (!to_local && bcast0(lds_ld(&hdr->snap)) != 0u) {
-        uint32_t got = 0;
+    uint32_t asker = 0;
+    if (bcast0(lds_ld(&hdr->req)) != 0u) {
+        uint32_t a = 0;
         if (lane == 0) {
-            uint32_t sv = lds_ld(&hdr->snap);
-            while (sv != 0u && !__hip_atomic_compare_exchange_weak(&hdr->snap, &sv, sv - 1u, __ATOMIC_RELAXED,
-                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            a = __hip_atomic_exchange(&hdr->req, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // a workgroup whose own wavefronts wait has nothing to spare
+            if (a != 0u && siblings_wait) {
+                st_dev(&sp.mail[a - 1u].state, kMailRefused);
+                a = 0u;
             }
-            got = sv != 0u;
         }
-        to_global = bcast0(got) != 0u;
+        asker = bcast0(a);
     }
-    if (!to_local && !to_global && lqn == 0u) to_local = true;
-    if (to_local || to_global) {
+    if (!to_local && asker == 0u && lqn == 0u) to_local = true;
+    bool gave = false;
+    if (to_local || asker != 0u) {
         for (uint32_t s = 0; s <= d; s++) {
             const uint32_t* f = frame(s);
             uint32_t Ls[WPL], Ps[WPL], Xs[WPL], cnt[WPL], incl[WPL];
@@ -852,8 +790,14 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
             // R of frame s: drop the children pushed from frames s..d-1
             for (uint32_t j = s; j < d; j++) clear_bit<WPL>(Rs, bcast0(frame(j)[3 * CS]), lane);
             bool ok;
-            if (to_global) {
-                ok = q_push<WPL>(sp, lane, g, W, Rs, Pd, Xd, L2);
+            if (asker != 0u) {
+                // the unit is in transit until the asker takes it: count it
+                // before it becomes visible
+                store_record<WPL>(sp.mail_rec + (size_t)(asker - 1u) * RW, CS, lane, g, W, Rs, Pd, Xd, L2);
+                if (lane == 0) __hip_atomic_fetch_add(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                vm_drain();
+                if (lane == 0) st_dev(&sp.mail[asker - 1u].state, kMailUnit);
+                ok = true;
             } else {
                 if (!wg_lock(hdr, lane, t_start, sp.watchdog_ticks)) return 1;
                 const uint32_t n = bcast0(lds_ld(&hdr->lq_n));
@@ -883,20 +827,32 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                     if (w < W) fw[2 * CS + w] = L1[c];
                 }
                 if (lane == 0) ctx->donations += 1;
+                gave = true;
             }
             break;
         }
     }
-    // Refresh the snapshot of hungry workgroups (the caller decides when: once
-    // per refresh_children children of the workgroup; paced by work done, not
-    // by a clock, because the real-time counter is slow to read from thousands
-    // of wavefronts).
+    if (asker != 0u && !gave && lane == 0) st_dev(&sp.mail[asker - 1u].state, kMailRefused);
+    // Look at this workgroup's mailbox (the caller decides when: once per
+    // refresh_children children of the workgroup; paced by work done, not by
+    // a clock, because the real-time counter is slow to read from thousands of
+    // wavefronts).  Only this workgroup and its askers touch that line.
     if (bcast0(refresh_v)) {
         uint32_t e = 0, rf = 0;
         if (lane == 0) {
-            const unsigned long long b = __hip_atomic_load(&sp.ctl->board, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t hg = (uint32_t)b, q = (uint32_t)(b >> 32);
-            lds_st(&hdr->snap, hg > q ? umin32(hg - q, 2u) : 0u);
+            if (lds_ld(&hdr->req) == 0u) {
+                unsigned int* mreq = &sp.mail[blockIdx.x].req;
+                if (ld_dev(mreq) != 0u) {
+                    const uint32_t a = __hip_atomic_exchange(mreq, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    uint32_t zero = 0u;
+                    // a sibling may have taken an earlier question meanwhile:
+                    // then this one is refused rather than lost
+                    if (a != 0u && !__hip_atomic_compare_exchange_strong(&hdr->req, &zero, a, __ATOMIC_RELAXED,
+                                                                         __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
+                        st_dev(&sp.mail[a - 1u].state, kMailRefused);
+                }
+            }
             rf = ++ctx->refreshes;
             if ((rf & 7u) == 0u) e = ld_dev(&sp.ctl->error);
         }
@@ -934,6 +890,14 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         ctx->spill_chunk = 0xffffffffu;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        // written by the root kernels, which ran before this one
+        const uint32_t ps = sp.ctl->pool_size;
+        hdr->pool_size = ps;
+        hdr->pool_left = ps != 0u;
+        hdr->rng = (blockIdx.x + 1u) * 0x9E3779B9u;
+    }
+    __syncthreads();
 
     const uint64_t t_start = wall_clock64();
     auto overdue = [&]() -> bool {
@@ -951,10 +915,12 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
     };
     set_state(kWaveIdle);
 
-    uint32_t backoff = 1, fetch_iters = 0, idle_iters = 0, polls = 1;
+    const uint32_t me = blockIdx.x;
+    uint32_t backoff = 1, idle_iters = 0, polls = 0;
     for (;;) {
         // ================= obtain a unit =================
-        // 1: from the LDS LIFO (slot lsl), 2: from HBM (ticket pos)
+        // src 1: the LDS LIFO (slot lsl), 2: the pool of root units (index
+        // pos), 3: this workgroup's mailbox
         uint32_t src = 0, lsl = 0, pos = 0;
         bool stop = false;
         for (;;) {
@@ -963,7 +929,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 const uint32_t n0 = bcast0(lds_ld(&hdr->lq_n));
                 const uint32_t dn0 = bcast0(lds_ld(&hdr->done));
                 const uint32_t f0 = bcast0(lds_ld(&hdr->fetcher));
-                if (n0 == 0u && dn0 == 0u && f0 != 0u) { // a sibling fetches for the workgroup
+                if (n0 == 0u && dn0 == 0u && f0 != 0u) { // a sibling looks for work
                     if ((++idle_iters & 255u) == 0u && overdue()) {
                         give_up();
                         stop = true;
@@ -993,12 +959,11 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 stop = true;
                 break;
             }
-            // This wavefront is idle and the LIFO is empty: it fetches for the
-            // workgroup unless a sibling already does.  The workgroup is then
-            // counted as waiting on the board (once, until it gets a unit
-            // from HBM), and leaves ctl->work if none of its wavefronts holds
-            // a unit any more.
-            uint32_t fetch = 0, went_inactive = 0, reg = 0, inactive = 0;
+            // This wavefront is idle and the LIFO is empty: it looks for work
+            // outside the workgroup unless a sibling already does.  The
+            // workgroup leaves ctl->work if none of its wavefronts holds a
+            // unit any more.
+            uint32_t fetch = 0, went_inactive = 0, inactive = 0;
             if (lane == 0 && lds_ld(&hdr->fetcher) == 0u) {
                 lds_st(&hdr->fetcher, 1u);
                 fetch = 1;
@@ -1007,31 +972,84 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                     went_inactive = 1;
                 }
                 inactive = lds_ld(&hdr->active) == 0u;
-                if (lds_ld(&hdr->hungry) == 0u) {
-                    lds_st(&hdr->hungry, 1u);
-                    reg = 1;
-                }
             }
             wg_unlock(hdr, lane);
             fetch = bcast0(fetch);
             inactive = bcast0(inactive);
-            if (lane == 0) {
-                if (reg) __hip_atomic_fetch_add(&sp.ctl->board, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (went_inactive)
-                    __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (fetch == 1) {
+            if (lane == 0 && went_inactive)
+                __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (fetch) {
                 set_state(kWaveFetch);
-                // look at the board once per poll_iters idle iterations
-                bool try_pop = false;
-                if (++fetch_iters >= sp.poll_iters) {
-                    fetch_iters = 0;
-                    polls++;
-                    unsigned long long b = 0;
-                    if (lane == 0) b = __hip_atomic_load(&sp.ctl->board, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    try_pop = bcast0((uint32_t)(b >> 32)) != 0u;
+                uint32_t kind = 0, p = 0, stop_now = 0;
+                if (lane == 0) {
+                    // (a) the answer to this workgroup's question.  A unit is
+                    // marked as being read, so that no later fetcher takes it
+                    // again or asks anew before the record slot is free.
+                    const uint32_t o = lds_ld(&hdr->out);
+                    if (o != 0u && o != kOutReading) {
+                        const uint32_t st = ld_dev(&sp.mail[me].state);
+                        if (st == kMailUnit) {
+                            kind = 3;
+                            lds_st(&hdr->out, kOutReading);
+                        } else if (st == kMailRefused) {
+                            st_dev(&sp.mail[me].state, kMailNone);
+                            lds_st(&hdr->out, 0u);
+                        }
+                    }
+                    // (b) a root unit from the pool
+                    if (kind == 0 && lds_ld(&hdr->pool_left) != 0u) {
+                        const uint32_t t = __hip_atomic_fetch_add(&sp.ctl->pool_next, 1u, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        if (t < lds_ld(&hdr->pool_size)) {
+                            kind = 2;
+                            p = t;
+                        } else {
+                            lds_st(&hdr->pool_left, 0u);
+                        }
+                    }
+                    // (c) a question to this workgroup while it holds no work:
+                    // refuse it (a busy workgroup answers from its checks)
+                    if (inactive) {
+                        uint32_t a = __hip_atomic_exchange(&hdr->req, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        unsigned int* mreq = &sp.mail[me].req;
+                        if (a == 0u && ld_dev(mreq) != 0u)
+                            a = __hip_atomic_exchange(mreq, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (a != 0u) st_dev(&sp.mail[a - 1u].state, kMailRefused);
+                    }
+                    // (d) ask a workgroup chosen at random
+                    if (kind == 0 && lds_ld(&hdr->out) == 0u && lds_ld(&hdr->pool_left) == 0u && sp.num_wg > 1u) {
+                        uint32_t x = lds_ld(&hdr->rng);
+                        x ^= x << 13;
+                        x ^= x >> 17;
+                        x ^= x << 5;
+                        lds_st(&hdr->rng, x);
+                        uint32_t v = (uint32_t)(((uint64_t)x * (sp.num_wg - 1u)) >> 32);
+                        if (v >= me) v++;
+                        uint32_t zero = 0u;
+                        if (__hip_atomic_compare_exchange_strong(&sp.mail[v].req, &zero, me + 1u, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                            lds_st(&hdr->out, v + 1u);
+                    }
+                    // (e) the end of the search, seen by a workgroup that holds no work
+                    if (kind == 0 && inactive && (++polls % sp.poll_iters) == 0u) {
+                        const uint32_t w = ld_dev(&sp.ctl->work);
+                        const uint32_t e = ld_dev(&sp.ctl->error);
+                        const bool late = (polls & 63u) == 0u && overdue();
+                        if (late) atomicOr(&sp.ctl->error, kErrWatchdog);
+                        if (w == 0u || e != 0u || late) stop_now = 1;
+                    }
                 }
-                if (try_pop && q_pop(sp, lane, &pos)) {
+                kind = bcast0(kind);
+                p = bcast0(p);
+                if (bcast0(stop_now)) {
+                    if (lane == 0) {
+                        lds_st(&hdr->done, 1u);
+                        lds_st(&hdr->fetcher, 0u);
+                    }
+                    stop = true;
+                    break;
+                }
+                if (kind != 0u) {
                     uint32_t was_active = 0;
                     if (!wg_lock(hdr, lane, t_start, sp.watchdog_ticks)) {
                         give_up();
@@ -1043,43 +1061,16 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                         lds_st(&hdr->active, 1u);
                         lds_st(&hdr->busy, lds_ld(&hdr->busy) + 1);
                         lds_st(&hdr->fetcher, 0u);
-                        lds_st(&hdr->hungry, 0u); // set by this or an earlier fetcher
                     }
                     wg_unlock(hdr, lane);
-                    if (lane == 0) {
-                        // one unit fewer in the queue, one waiting workgroup fewer
-                        __hip_atomic_fetch_sub(&sp.ctl->board, (1ull << 32) + 1ull, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                        // the unit's count is already covered by this workgroup
-                        if (was_active)
-                            __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    src = 2;
+                    // the unit's count is already covered by this workgroup
+                    if (lane == 0 && was_active)
+                        __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    src = kind;
+                    pos = p;
                     break;
                 }
-                if (inactive && (polls & 1u) == 0u) {
-                    // only a workgroup that holds no work can see the end
-                    polls++;
-                    uint32_t w = 0, e = 0;
-                    if (lane == 0) {
-                        w = ld_dev(&sp.ctl->work);
-                        e = ld_dev(&sp.ctl->error);
-                    }
-                    w = bcast0(w);
-                    e = bcast0(e);
-                    const bool late = (polls & 63u) == 0u && overdue();
-                    if (late && lane == 0) atomicOr(&sp.ctl->error, kErrWatchdog);
-                    if (lane == 0) {
-                        if (w == 0u || e != 0u || late) lds_st(&hdr->done, 1u);
-                        lds_st(&hdr->fetcher, 0u);
-                    }
-                    if (w == 0u || e != 0u || late) {
-                        stop = true;
-                        break;
-                    }
-                } else if (lane == 0) {
-                    lds_st(&hdr->fetcher, 0u);
-                }
+                if (lane == 0) lds_st(&hdr->fetcher, 0u);
             }
             for (uint32_t i = 0; i < backoff; i++) __builtin_amdgcn_s_sleep(8);
             if (backoff < 8) backoff <<= 1;
@@ -1091,7 +1082,8 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         // ================= load the unit =================
         const uint32_t CS = sp.w32cap, SW = sp.slot_words;
         const uint32_t* rec = (src == 1) ? (lq + (size_t)lsl * RW)
-                                         : (sp.rec + (size_t)(pos & sp.cap_mask) * sp.rec_words);
+                            : (src == 2) ? (sp.rec + (size_t)pos * RW)
+                                         : (sp.mail_rec + (size_t)me * RW);
         const uint32_t g = bcast0(src == 1 ? rec[0] : ld_dev(&rec[0]));
         const uint32_t W = bcast0(sp.graphs[g].w32);
         uint32_t Rb[WPL], P[WPL], X[WPL], L[WPL], roff[WPL];
@@ -1112,8 +1104,16 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
             }
             roff[c] = in ? w : (W - 1u);
         }
-        if (src == 1) wg_unlock(hdr, lane);
-        else q_release_slot(sp, lane, pos);
+        if (src == 1) {
+            wg_unlock(hdr, lane);
+        } else if (src == 3) {
+            // the record is read: the mailbox may take the next answer
+            vm_drain();
+            if (lane == 0) {
+                st_dev(&sp.mail[me].state, kMailNone);
+                lds_st(&hdr->out, 0u);
+            }
+        }
         if (g != bcast0(ctx->g)) {
             cold_fold(spp, wl);
             if (lane == 0) ctx->g = g;
@@ -1303,7 +1303,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 const uint32_t busy = bcast0(lds_ld(&hdr->busy));
                 const uint32_t lqn = bcast0(lds_ld(&hdr->lq_n));
                 const uint32_t dn = bcast0(lds_ld(&hdr->done));
-                const uint32_t snap = bcast0(lds_ld(&hdr->snap));
+                const uint32_t asked = bcast0(lds_ld(&hdr->req));
                 uint32_t tk = 0;
                 if (lane == 0)
                     tk = __hip_atomic_fetch_add(&hdr->ticks, cimask + 1u, __ATOMIC_RELAXED,
@@ -1314,7 +1314,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                     abort = true;
                     break;
                 }
-                if (refresh || snap || lqn == 0u || (lqn < kLocalSlots && NW - busy > lqn)) {
+                if (refresh || asked || lqn == 0u || (lqn < kLocalSlots && NW - busy > lqn)) {
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
                         const uint32_t w = (uint32_t)c * 64u + lane;
@@ -1405,15 +1405,15 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
 }
 
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
-                        uint32_t cap, uint32_t workgroups, hipStream_t s)
+                        uint32_t workgroups, hipStream_t s)
 {
     uint64_t work = hist_total;
-    if (work < cap) work = cap;
+    if (work < (uint64_t)workgroups * (sizeof(Mailbox) / 4)) work = (uint64_t)workgroups * (sizeof(Mailbox) / 4);
     if (work < (uint64_t)num_graphs * 8) work = (uint64_t)num_graphs * 8;
     uint32_t blocks = (uint32_t)((work + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, sp, num_graphs, hist_total, cap, workgroups);
+    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, sp, num_graphs, hist_total, workgroups);
     return hipGetLastError();
 }
 

@@ -45,14 +45,13 @@ struct DevResult {
     unsigned int unit_base, unit_count; // queue slots of the graph's root units
 };
 
-// Control block of one search launch.  The words every workgroup polls sit
+// Control block of one search launch.  Words written by many workgroups sit
 // on cache lines of their own.
 struct QueueCtl {
-    unsigned int head, pad_h[31];     // HBM queue: next ticket to consume
-    unsigned int tail, pad_t[31];     // HBM queue: next ticket to produce
-    unsigned int work, pad_w[31];     // units in the HBM queue + workgroups holding work
-    unsigned long long board;         // low 32 bits: workgroups waiting for a unit from HBM,
-    unsigned long long pad_g[15];     // high 32 bits: units published in the HBM queue
+    unsigned int pool_next, pad_h[31]; // next root unit to hand out
+    unsigned int pool_size, pad_t[31]; // root units written by the root kernels
+    unsigned int work, pad_w[31];      // root units not handed out + units in transit
+                                       // + workgroups holding work; the search ends at 0
     unsigned int error, pad_e[31];
     unsigned long long donations, units;
     unsigned long long spill_next;           // next free chunk of the spill pool
@@ -60,6 +59,18 @@ struct QueueCtl {
     unsigned long long vcursor, ocursor;     // enumerate output cursors
     unsigned long long pad_s[2];
 };
+
+// Mailbox of one search workgroup in HBM.  A workgroup out of work asks one
+// other workgroup at a time: it writes its id + 1 into that workgroup's req
+// word (compare-and-swap from 0), and the asked workgroup answers in the
+// asker's state word: a unit (copied to the asker's record slot first) or a
+// refusal.  Each word has a cache line of its own.
+struct Mailbox {
+    unsigned int req, pad_r[31];   // asking workgroup + 1, 0: none
+    unsigned int state, pad_s[31]; // answer to this workgroup's own question
+};
+constexpr unsigned int kMailNone = 0u, kMailUnit = 1u, kMailRefused = 2u;
+
 // QueueCtl.error bits
 constexpr unsigned int kErrSpill = 1u; // spill pool exhausted: rerun with a larger pool
 constexpr unsigned int kErrDepth = 2u; // stack deeper than a spill chunk (a bug)
@@ -72,13 +83,14 @@ struct SearchParams {
     DevResult* results;
     unsigned long long* hist;
     QueueCtl* ctl;
-    unsigned int* seq;        // queue sequence numbers, cap entries
-    uint32_t* rec;            // queue records, cap * rec_words
+    uint32_t* rec;            // root units, cap * rec_words
+    Mailbox* mail;            // one per workgroup
+    uint32_t* mail_rec;       // one record slot per workgroup, rec_words each
     uint32_t* spill;          // per wavefront: spill_levels * slot_words
     uint32_t* verts;          // enumerate output (device) or nullptr
     unsigned long long* offs;
     unsigned long long verts_cap, offs_cap;
-    uint32_t cap_mask;
+    uint32_t num_wg;          // search workgroups
     uint32_t rec_words;       // kRecHeader + 4 * w32cap
     uint32_t w32cap;          // bitset stride in LDS slots and records
     uint32_t slot_words;      // 3 * w32cap + 1
@@ -90,8 +102,8 @@ struct SearchParams {
     uint32_t check_interval;
     uint32_t enumerate;
     uint64_t watchdog_ticks;  // wall-clock ticks a wavefront may run (0 = no limit)
-    uint32_t refresh_children; // children a workgroup processes between two looks at the board
-    uint32_t poll_iters;       // idle iterations between two looks of a hungry workgroup
+    uint32_t refresh_children; // children a workgroup processes between two looks at its mailbox
+    uint32_t poll_iters;       // idle iterations between two looks at the end-of-search counter
     uint32_t* wave_state;     // per wavefront: kWave* phase (for deadline reports), or null
 };
 // Phases recorded in SearchParams.wave_state.
@@ -112,7 +124,7 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
                           const uint64_t* rows_in, const uint32_t* order, uint32_t* adj,
                           hipStream_t s);
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
-                        uint32_t cap, uint32_t workgroups, hipStream_t s);
+                        uint32_t workgroups, hipStream_t s);
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
                        uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s);
 hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,

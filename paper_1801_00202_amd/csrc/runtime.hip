@@ -293,7 +293,7 @@ struct mce_graph_s {
     uint64_t in_words = 0, adj_words = 0, ord_words = 0, hist_total = 0;
     DevBuf d_desc, d_in, d_adj, d_order;
     // workspace of the solve
-    DevBuf d_results, d_hist, d_ctl, d_seq, d_rec, d_spill, d_state, d_params;
+    DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params;
     HostPinned h_params; // staging of the search parameters (stable for graph replays)
     HostPinned h_out; // results | ctl | hist, copied back in one go
     LaunchCfg cfg;
@@ -372,9 +372,10 @@ int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
     if ((rc = h->d_results.ensure(sizeof(DevResult) * h->num_graphs)) != MCE_OK) return rc;
     if ((rc = h->d_hist.ensure(8 * std::max<uint64_t>(h->hist_total, 1))) != MCE_OK) return rc;
     if ((rc = h->d_ctl.ensure(sizeof(QueueCtl))) != MCE_OK) return rc;
-    if ((rc = h->d_seq.ensure(4ull * c.cap)) != MCE_OK) return rc;
     const uint64_t rec_words = kRecHeader + 4ull * c.w32cap;
     if ((rc = h->d_rec.ensure(4ull * rec_words * c.cap)) != MCE_OK) return rc;
+    if ((rc = h->d_mail.ensure(sizeof(Mailbox) * (uint64_t)c.blocks)) != MCE_OK) return rc;
+    if ((rc = h->d_mail_rec.ensure(4ull * rec_words * c.blocks)) != MCE_OK) return rc;
     const uint64_t spill = 4ull * c.slot_words * c.spill_levels * c.spill_chunks;
     if ((rc = h->d_spill.ensure(spill)) != MCE_OK) return rc;
     if ((rc = h->d_state.ensure(4ull * c.blocks * c.wpb)) != MCE_OK) return rc;
@@ -394,11 +395,12 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
     sp.results = h->d_results.as<DevResult>();
     sp.hist = h->d_hist.as<unsigned long long>();
     sp.ctl = h->d_ctl.as<QueueCtl>();
-    sp.seq = h->d_seq.as<unsigned int>();
     sp.rec = h->d_rec.as<uint32_t>();
+    sp.mail = h->d_mail.as<Mailbox>();
+    sp.mail_rec = h->d_mail_rec.as<uint32_t>();
+    sp.num_wg = c.blocks;
     sp.spill = h->d_spill.as<uint32_t>();
     sp.wave_state = h->d_state.as<uint32_t>();
-    sp.cap_mask = c.cap - 1;
     sp.rec_words = kRecHeader + 4 * c.w32cap;
     sp.w32cap = c.w32cap;
     sp.slot_words = c.slot_words;
@@ -412,10 +414,11 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
     DeviceInfo di;
     const bool have_clock = device_info(&di) == MCE_OK && di.wall_khz > 0;
     if (o.watchdog_ms > 0 && have_clock) sp.watchdog_ticks = (uint64_t)o.watchdog_ms * (uint64_t)di.wall_khz;
-    // a busy workgroup looks at the board every refresh_children children
-    sp.refresh_children = o.refresh_children > 0 ? (uint32_t)o.refresh_children : 512u;
+    // a busy workgroup looks at its mailbox every refresh_children children
+    sp.refresh_children = o.refresh_children > 0 ? (uint32_t)o.refresh_children : 128u;
     if (sp.refresh_children < sp.check_interval) sp.refresh_children = sp.check_interval;
-    sp.poll_iters = 4;
+    // an idle workgroup reads the end-of-search counter every poll_iters looks
+    sp.poll_iters = 8;
     return sp;
 }
 
@@ -423,9 +426,9 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
 int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, uint64_t first,
                   uint64_t last, hipStream_t s, bool timed)
 {
-    HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.cap, c.blocks, s));
-    // the root children fill at most half of the queue; donations use the rest
-    const uint32_t max_units = std::max<uint32_t>(1u, (c.cap / 2u) / h->num_graphs);
+    HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.blocks, s));
+    // the root children of all graphs fill at most the pool
+    const uint32_t max_units = std::max<uint32_t>(1u, c.cap / h->num_graphs);
     HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, max_units, s));
     std::memcpy(h->h_params.p, &sp, sizeof(sp));
     HIP_TRY(hipMemcpyAsync(h->d_params.p, h->h_params.p, sizeof(sp), hipMemcpyHostToDevice, s));
@@ -565,9 +568,9 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
                 for (uint32_t x : st) n[x < 5 ? x : 0]++;
             std::fprintf(stderr,
                          "libmce: search stopped by the watchdog (error bits %u); wavefronts: %u idle, "
-                         "%u fetching, %u busy, %u exited, %u never started; work %u hungry %u queue %u\n",
+                         "%u fetching, %u busy, %u exited, %u never started; work %u, root units %u of %u taken\n",
                          ctl.error, n[kWaveIdle], n[kWaveFetch], n[kWaveBusy], n[kWaveExited], n[0], ctl.work,
-                         (uint32_t)ctl.board, ctl.tail - ctl.head);
+                         std::min(ctl.pool_next, ctl.pool_size), ctl.pool_size);
             return MCE_E_DEVICE;
         }
         if (ctl.error & kErrSpill) {
@@ -977,8 +980,8 @@ uint64_t job_footprint(mce_graph_s* h)
     LaunchCfg c;
     if (make_cfg(h, &c, 0) != MCE_OK) return 0;
     const uint64_t rec_words = kRecHeader + 4ull * c.w32cap;
-    return sizeof(DevResult) * h->num_graphs + 8ull * h->hist_total + 4ull * c.cap * (1 + rec_words) +
-           4ull * c.slot_words * c.spill_levels * c.spill_chunks;
+    return sizeof(DevResult) * h->num_graphs + 8ull * h->hist_total + 4ull * c.cap * rec_words +
+           (sizeof(Mailbox) + 4ull * rec_words) * c.blocks + 4ull * c.slot_words * c.spill_levels * c.spill_chunks;
 }
 
 void worker_loop(uint32_t slot)
