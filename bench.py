@@ -1,22 +1,29 @@
 """Benchmark of the MI355X GreedyBB maximal clique enumeration.
 
 One step = one pass of the whole hot path over one synthetic graph already
-resident in HBM: device-side validation, maximum-degree-first ordering,
-renumbering (mce_prepare with a device pointer), the root and the persistent
-search with its work queue, the reduction and the copy of the results to the
-host (mce_count), then mce_release.
+resident in HBM: device-side validation, maximum-degree-first ordering and
+renumbering (mce_prepare with a device pointer), the root units and the
+persistent search with its work distribution, the reduction and the copy of
+the totals to the host (mce_count), then mce_release.
 
 Default workload: G(n=1000, p=0.3), seed 0 -- the random graph of the paper's
-Table 1 (n = 1000, p = 0.3) drawn with this repository's seeded generator.
+Table 1 row (n = 1000, p = 0.3), drawn with this repository's seeded
+generator.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build runs on
 one GPU.
+
+``--copy-probe`` instead times a plain device-to-device copy of known size;
+run under ``rocprofv3 --pmc FETCH_SIZE`` (then ``WRITE_SIZE``) it calibrates the
+HBM byte counters that the ``traffic`` figure of the search kernel uses.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,8 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X peak of 32-bit integer vector lane operations: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz.
-VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# 16 lanes x 2.4 GHz (bitwise integer ops have no packed form).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Paper, Table 1, GreedyBB at n=1000, p=0.3 (average of 10 graphs, one Xeon
 # E5-2690 v2 core): 15.487755M maximal cliques in 4.964 s.
 PAPER_G1000_CLIQUES_PER_S = 15.487755e6 / 4.964
@@ -35,6 +42,13 @@ WORKLOADS = {
     "gnp100": dict(n=100, p=0.5, seed=0),
     "gnp300_05": dict(n=300, p=0.5, seed=0),
 }
+KERNEL_SRC = os.path.join(ROOT, "paper_1801_00202_amd", "csrc", "kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "search_kernel_gnp1000_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def algorithmic_word_ops(res: dict, n: int) -> int:
@@ -45,12 +59,33 @@ def algorithmic_word_ops(res: dict, n: int) -> int:
     return w * (2 * res["nodes"] + 4 * res["children"])
 
 
-def cpu_baseline(rows, threads: int) -> dict:
-    import oracle
+def recorded_traffic(workload: str):
+    """HBM bytes per search-kernel launch from the committed counter summary,
+    or None if it was taken on another kernel source or workload."""
+    if workload != "gnp1000" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", open(TRAFFIC_PROFILE).read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_sha256_16") != kernel_source_hash():
+        return None
+    return rec
+
+
+def copy_probe(mib: int, reps: int) -> None:
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ref = oracle.greedy(rows, threads=threads)
-    dt = time.perf_counter() - t0
-    return ref, dt
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "reps": reps,
+                      "GB_per_s": 8 * n / dt / 1e9}))
 
 
 def main():
@@ -61,12 +96,16 @@ def main():
     ap.add_argument("--workload", default="gnp1000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, max(args.steps, 1))
+        return
 
     import numpy as np
     import torch
@@ -108,7 +147,8 @@ def main():
     nodes_per_s = first["nodes"] * args.steps / dt
     k_us = sum(kernel_us) / len(kernel_us)
     ops = algorithmic_word_ops(first, wl["n"])
-    achieved = ops / (k_us * 1e-6) / 1e9
+    achieved = ops / (k_us * 1e-6) / 1e12
+    traffic = recorded_traffic(args.workload)
 
     line = {
         "metric": "maximal cliques/sec (GreedyBB, one GPU)",
@@ -124,23 +164,30 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "G(n=%d, p=%g) seed %d" % (wl["n"], wl["p"], wl["seed"]),
-                   "cliques": first["count"], "nodes": first["nodes"], "omega": first["omega"]},
+                   "cliques": first["count"], "nodes": first["nodes"], "children": first["children"],
+                   "omega": first["omega"]},
         "nodes_per_s": nodes_per_s,
-        "search_kernel_us": k_us,
-        "prepare_us": sum(s["prepare_us"] for s in stats) / len(stats),
+        "search_kernel_ms": k_us / 1e3,
+        "prepare_ms": sum(s["prepare_us"] for s in stats) / len(stats) / 1e3,
         "launch": {"blocks": stats[0]["blocks"], "waves_per_block": stats[0]["waves_per_block"],
                    "lds_depth": stats[0]["lds_depth"], "donations": stats[0]["donations"],
                    "units": stats[0]["units"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
-                     "frac": achieved / VALU_PEAK_GOPS, "traffic": None},
+        "roofline": {"bound": "alu", "kernel": "search_kernel", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "T int32 lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "ops_per_launch": ops,
+                     "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"]},
     }
     if not args.no_cpu_baseline:
+        import oracle
         threads = args.cpu_threads or min(len(os.sched_getaffinity(0)), 16)
-        ref, cdt = cpu_baseline(rows, threads)
+        c0 = time.perf_counter()
+        ref = oracle.greedy(rows, threads=threads)
+        cdt = time.perf_counter() - c0
         assert ref["count"] == first["count"] and ref["hash_xor"] == first["hash_xor"]
         line["cpu_baseline"] = {"value": ref["count"] / cdt, "unit": "cliques/s", "cores": threads,
-                                "kind": "oracle",
-                                "sample": "the full workload graph, root children shared among threads"}
+                                "kind": "oracle", "seconds": cdt,
+                                "sample": "one full solve of the workload graph, root children shared "
+                                          "among the threads"}
     print(json.dumps(line))
 
 

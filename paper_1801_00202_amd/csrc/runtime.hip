@@ -536,7 +536,8 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
                 hipGraph_t graph = nullptr;
                 hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    rc = enqueue_solve(g, c, sp, first, last, cs, false);
+                    // the events around the search kernel become nodes of the graph
+                    rc = enqueue_solve(g, c, sp, first, last, cs, true);
                     e = hipStreamEndCapture(cs, &graph);
                 }
                 (void)hipStreamDestroy(cs);
@@ -583,9 +584,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         mce_stats_t st;
         std::memset(&st, 0, sizeof(st));
         if (hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess) st.search_us = ms * 1000.0;
-        if (!(use_graph && !enumerate && first == 0 && last == UINT64_MAX) &&
-            hipEventElapsedTime(&ms, g->ev[2], g->ev[3]) == hipSuccess)
-            st.search_kernel_us = ms * 1000.0;
+        if (hipEventElapsedTime(&ms, g->ev[2], g->ev[3]) == hipSuccess) st.search_kernel_us = ms * 1000.0;
         st.prepare_us = g->prepare_ms * 1000.0;
         st.blocks = c.blocks;
         st.waves_per_block = c.wpb;
