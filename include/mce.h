@@ -9,7 +9,7 @@
  *     vertex of X in the ordering if X is non-empty, else the first of P,
  *   - the bitset encoding of Sec. 4.1 (P, X, L = P \ N(p) as bitstrings).
  * The search runs on one AMD Instinct MI355X (gfx950) as a persistent HIP
- * kernel, one wavefront per subproblem, with a device work queue.
+ * kernel, one wavefront per subproblem, with on-device work distribution.
  *
  * Graph input format (all entry points): adjacency bitset rows of uint64
  * words, least significant bit first.  Bit j of row i is set iff {i, j} is an
@@ -64,14 +64,15 @@ extern "C" {
 #define MCE_OPT_LDS_DEPTH 3        /* stack levels kept in LDS per wavefront, 0..64 (rest spill to HBM) */
 #define MCE_OPT_SPLIT_THRESHOLD 4  /* hand over only frames whose P holds at least this many
                                       vertices (0 = auto) */
-#define MCE_OPT_CHECK_INTERVAL 5   /* children between two looks at the queue, >= 1 */
-#define MCE_OPT_QUEUE_CAP 6        /* queue capacity in units (power of two, 0 = auto) */
+#define MCE_OPT_CHECK_INTERVAL 5   /* children a wavefront examines between two looks at its
+                                      siblings and the mailbox, >= 1 (rounded up to a power of two) */
+#define MCE_OPT_QUEUE_CAP 6        /* capacity of the pool of root units (power of two, 0 = auto) */
 #define MCE_OPT_WATCHDOG_MS 7      /* stop a search after this many ms and fail with
                                       MCE_E_DEVICE (0 = no limit, the default) */
 #define MCE_OPT_GRAPH 8            /* mce_count replays a captured hipGraph of the solve:
                                       0 never, 1 for batch handles (default), 2 always */
 #define MCE_OPT_REFRESH_CHILDREN 9 /* children a busy workgroup processes between two looks
-                                      for hungry workgroups (0 = auto) */
+                                      at its mailbox for workgroups asking for work (0 = auto) */
 
 typedef struct mce_graph_s *mce_graph_t; /* opaque; owns the device copy, order and rows */
 
