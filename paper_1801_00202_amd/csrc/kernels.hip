@@ -171,6 +171,34 @@ __device__ __forceinline__ void set_bit(uint32_t (&s)[WPL], uint32_t v, uint32_t
         if ((wi >> 6) == (uint32_t)c) s[c] = (lane == (wi & 63)) ? (s[c] | m) : s[c];
 }
 
+// Position of the lowest set bit, or -1: the lane's candidate position is
+// formed on the vector side and one lane is read, so the scalar side does a
+// single find-first.  lane_lo[c] = 32 * (64 c + lane).
+template <int WPL>
+__device__ __forceinline__ int first_pos(const uint32_t (&s)[WPL], const uint32_t (&lane_lo)[WPL])
+{
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint64_t m = ballot(s[c] != 0u);
+        if (m) {
+            const uint32_t pos = lane_lo[c] | (uint32_t)__builtin_ctzg(s[c], 32);
+            return (int)rdlane(pos, (uint32_t)__builtin_ctzll(m));
+        }
+    }
+    return -1;
+}
+
+// The one-bit mask of position v (uniform) in this lane's words.
+template <int WPL>
+__device__ __forceinline__ void bit_mask(uint32_t v, const uint32_t (&lane_lo)[WPL], uint32_t (&m)[WPL])
+{
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t d = v - lane_lo[c];
+        m[c] = d < 32u ? (1u << (d & 31u)) : 0u;
+    }
+}
+
 // Inclusive prefix of popcounts over all words (chunk-major), and the total.
 template <int WPL>
 __device__ __forceinline__ uint32_t popc_scan(const uint32_t (&s)[WPL], uint32_t (&cnt)[WPL],
@@ -314,7 +342,7 @@ __global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, co
     const uint32_t n = gd.n;
     const uint32_t* ord = order + gd.ord_off;
     const uint64_t* src = rows_in + gd.in_off + (uint64_t)ord[i] * gd.rw64;
-    uint32_t* dst = adj + gd.adj_off + (uint64_t)i * gd.w32;
+    uint32_t* dst = adj + gd.adj_off + (uint64_t)i * gd.rstride;
     for (uint32_t w = threadIdx.x; w < gd.w32; w += blockDim.x) {
         uint32_t val = 0;
         for (uint32_t b = 0; b < 32; b++) {
@@ -325,6 +353,9 @@ __global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, co
         }
         dst[w] = val;
     }
+    // the word after the row holds the vertex's input id, so that the search
+    // gets it with the row
+    if (threadIdx.x == 0 && gd.rstride > gd.w32) dst[gd.w32] = ord[i];
 }
 
 // Zero the per-graph results, the histograms, the control block and the
@@ -515,14 +546,15 @@ __device__ __forceinline__ void wg_unlock(WgHdr* h, uint32_t lane)
 
 // Per-wavefront LDS layout (32-bit words):
 //   [kOffHist, +128)   histogram of clique sizes < kHistLds (u64)
-//   [kOffAcc,  +256)   per lane: XOR and sum of the hashes of flushed cliques (u64 each)
-//   [kOffCent, +64)    clique buffer entries: start | size << 16
-//   [kOffCids, +kCliqueIds/2)  clique buffer ids (u16)
-//   [kOffCtx,  +32)    WaveCtx: totals and bookkeeping used off the hot path
-//   [kWaveFixedWords, +slot_words)  the current frame, written before a check
-//   then lds_depth stack frames of slot_words each
-constexpr uint32_t kOffHist = 0, kOffAcc = 128, kOffCent = 384, kOffCids = 448, kOffCtx = kOffCids + kCliqueIds / 2;
-static_assert(kOffCids + kCliqueIds / 2 == kOffCtx, "layout");
+//   [kOffBuf, +kCliqueSlots)  clique buffer (16-bit halves of input-id bitsets)
+//   [kOffTrash, +64)   one word per lane for stores that must go nowhere
+//   [kOffCtx, +32)     WaveCtx: totals and bookkeeping used off the hot path
+//   [kWaveFixedWords, ...)  lds_depth stack frames, then the slot of the
+//                      current frame (written before a check), then slack
+// A frame holds P, X and L interleaved per lane: lane w's words of chunk c
+// sit at 3 (64 c + w) .. +2.
+constexpr uint32_t kOffHist = 0, kOffBuf = kHistLds * 2, kOffTrash = kOffBuf + kCliqueSlots,
+                   kOffCtx = kOffTrash + 64;
 static_assert(kOffCtx + 32 == kWaveFixedWords, "layout");
 
 struct WaveCtx {
@@ -541,31 +573,46 @@ template <int WPL> struct LaneBits {
     uint32_t w[WPL];
 };
 
-// Hash, histogram and (enumerate) write-out of the nent buffered cliques; one
-// clique per lane.  Off the hot path.
-__device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restrict__ spp, uint32_t* wl,
-                                                     uint32_t nent_v, uint32_t used_v, uint32_t hist_off_lo,
-                                                     uint32_t hist_off_hi)
+// Per-lane XOR and sum of the hashes of flushed cliques, kept in registers.
+struct LaneAcc {
+    uint64_t x, s;
+};
+
+// Hash, histogram and (enumerate) write-out of the nent buffered cliques, one
+// clique per lane: lane i's clique is the list of halves at buffer words
+// [start, start + cnt), with cent (this lane's value) = start << 16 | cnt.
+// Off the hot path.
+__device__ __attribute__((noinline)) LaneAcc cold_flush(const SearchParams* __restrict__ spp, uint32_t* wl,
+                                                        uint32_t cent, uint32_t nent_v, uint32_t hist_off_lo,
+                                                        uint32_t hist_off_hi, LaneAcc acc)
 {
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
-    const uint32_t nent = bcast0(nent_v), used = bcast0(used_v);
+    const uint32_t nent = bcast0(nent_v);
     const uint64_t hoff = ((uint64_t)bcast0(hist_off_hi) << 32) | bcast0(hist_off_lo);
     unsigned long long* ghist = sp.hist + hoff;
     unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl + kOffHist);
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(wl + kOffAcc);
-    const uint32_t* cent = wl + kOffCent;
-    const uint16_t* cids = reinterpret_cast<const uint16_t*>(wl + kOffCids);
+    const uint32_t* buf = wl + kOffBuf;
     WaveCtx* ctx = wave_ctx(wl);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     const bool mine = lane < nent;
-    const uint32_t e = mine ? cent[lane] : 0u;
-    const uint32_t st = e & 0xffffu, k = e >> 16;
+    const uint32_t st = mine ? (cent >> 16) : 0u, cnt = mine ? (cent & 0xffffu) : 0u;
+    // clique size, then the hash chain over the ids in increasing order
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < cnt; i++) k += (uint32_t)__builtin_popcount(buf[st + i] & 0xffffu);
     if (mine) {
         uint64_t h = mix64((uint64_t)k);
-        for (uint32_t j = 0; j < k; j++) h = mix64(h + kGolden + (uint64_t)cids[st + j]);
-        acc[lane] ^= h;
-        acc[64 + lane] += h;
+        for (uint32_t i = 0; i < cnt; i++) {
+            const uint32_t e = buf[st + i];
+            const uint32_t base = (e >> 16) << 4;
+            uint32_t bits = e & 0xffffu;
+            while (bits) {
+                h = mix64(h + kGolden + (uint64_t)(base + (uint32_t)__builtin_ctz(bits)));
+                bits &= bits - 1u;
+            }
+        }
+        acc.x ^= h;
+        acc.s += h;
     }
     uint64_t rem = ballot(mine);
     uint32_t kmax = 0;
@@ -586,6 +633,10 @@ __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restr
         ctx->omega = umax32(ctx->omega, kmax);
     }
     if (sp.enumerate) {
+        // ids of clique i at verts[vb + (sizes of cliques before i)], and its
+        // [begin, end) pair at offs[ob + 2 i]
+        const uint32_t kincl = wave_scan_incl(mine ? k : 0u);
+        const uint32_t used = rdlane(kincl, 63);
         unsigned long long vb = 0, ob = 0;
         if (lane == 0) {
             vb = atomicAdd(&sp.ctl->vcursor, (unsigned long long)used);
@@ -593,82 +644,29 @@ __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restr
         }
         vb = ((unsigned long long)bcast0((uint32_t)(vb >> 32)) << 32) | bcast0((uint32_t)vb);
         ob = ((unsigned long long)bcast0((uint32_t)(ob >> 32)) << 32) | bcast0((uint32_t)ob);
-        if (vb + used <= sp.verts_cap && ob + 2ull * nent <= sp.offs_cap) {
-            for (uint32_t i = lane; i < used; i += 64) sp.verts[vb + i] = cids[i];
-            if (mine) {
-                sp.offs[ob + 2ull * lane] = vb + st;
-                sp.offs[ob + 2ull * lane + 1ull] = vb + st + k;
+        if (vb + used <= sp.verts_cap && ob + 2ull * nent <= sp.offs_cap && mine) {
+            unsigned long long q = vb + kincl - k;
+            sp.offs[ob + 2ull * lane] = q;
+            sp.offs[ob + 2ull * lane + 1ull] = q + k;
+            for (uint32_t i = 0; i < cnt; i++) {
+                const uint32_t e = buf[st + i];
+                const uint32_t base = (e >> 16) << 4;
+                uint32_t bits = e & 0xffffu;
+                while (bits) {
+                    sp.verts[q++] = base + (uint32_t)__builtin_ctz(bits);
+                    bits &= bits - 1u;
+                }
             }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    return acc;
 }
 
-// A clique too large for the buffer: hashed in place on the scalar unit.
-template <int WPL>
-__device__ __attribute__((noinline)) void cold_big_clique(const SearchParams* __restrict__ spp, uint32_t* wl,
-                                                          LaneBits<WPL> cwb, uint32_t hist_off_lo,
-                                                          uint32_t hist_off_hi)
-{
-    const uint32_t (&cw)[WPL] = cwb.w;
-    const SearchParams& sp = *spp;
-    const uint32_t lane = lane_id();
-    const uint64_t hoff = ((uint64_t)bcast0(hist_off_hi) << 32) | bcast0(hist_off_lo);
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(wl + kOffAcc);
-    WaveCtx* ctx = wave_ctx(wl);
-    uint32_t cnt[WPL], incl[WPL];
-    const uint32_t k = popc_scan<WPL>(cw, cnt, incl);
-    uint64_t h = mix64((uint64_t)k);
-#pragma unroll
-    for (int c = 0; c < WPL; c++) {
-        uint64_t m = ballot(cw[c] != 0);
-        while (m) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(m);
-            m &= m - 1;
-            uint32_t w = rdlane(cw[c], l);
-            while (w) {
-                const uint32_t b = (uint32_t)__builtin_ctz(w);
-                w &= w - 1;
-                h = mix64(h + kGolden + (uint64_t)((((uint32_t)c * 64u + l) << 5) | b));
-            }
-        }
-    }
-    if (lane == 0) {
-        acc[0] ^= h;
-        acc[64] += h;
-        atomicAdd(&sp.hist[hoff + k], 1ull);
-        ctx->count += 1;
-        ctx->omega = umax32(ctx->omega, k);
-    }
-    if (sp.enumerate) {
-        unsigned long long vb = 0, ob = 0;
-        if (lane == 0) {
-            vb = atomicAdd(&sp.ctl->vcursor, (unsigned long long)k);
-            ob = atomicAdd(&sp.ctl->ocursor, 2ull);
-        }
-        vb = ((unsigned long long)bcast0((uint32_t)(vb >> 32)) << 32) | bcast0((uint32_t)vb);
-        ob = ((unsigned long long)bcast0((uint32_t)(ob >> 32)) << 32) | bcast0((uint32_t)ob);
-        if (vb + k <= sp.verts_cap && ob + 2ull <= sp.offs_cap) {
-#pragma unroll
-            for (int c = 0; c < WPL; c++) {
-                uint64_t p = vb + incl[c] - cnt[c];
-                uint32_t x = cw[c];
-                const uint32_t wb = ((uint32_t)c * 64u + lane) << 5;
-                while (x) {
-                    sp.verts[p++] = wb | (uint32_t)__builtin_ctz(x);
-                    x &= x - 1;
-                }
-            }
-            if (lane == 0) {
-                sp.offs[ob] = vb;
-                sp.offs[ob + 1] = vb + k;
-            }
-        }
-    }
-}
-
-// Fold the wavefront's totals of graph ctx->g into HBM and clear them.
-__device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restrict__ spp, uint32_t* wl)
+// Fold the wavefront's totals of graph ctx->g (and its hash accumulators)
+// into HBM and clear them.
+__device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restrict__ spp, uint32_t* wl,
+                                                    LaneAcc acc)
 {
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
@@ -676,10 +674,7 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
     const uint32_t g = bcast0(ctx->g);
     if (g == 0xffffffffu) return;
     unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl + kOffHist);
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(wl + kOffAcc);
-    uint64_t x = acc[lane], s = acc[64 + lane];
-    acc[lane] = 0;
-    acc[64 + lane] = 0;
+    uint64_t x = acc.x, s = acc.s;
     for (int off = 32; off > 0; off >>= 1) {
         x ^= __shfl_xor(x, off);
         s += __shfl_xor(s, off);
@@ -713,7 +708,8 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
 template <int WPL>
 __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __restrict__ spp, uint32_t* smem,
                                                          uint32_t* wl, uint32_t d_v, uint32_t W_v, uint32_t g_v,
-                                                         LaneBits<WPL> Rbb, uint64_t t_start, uint32_t refresh_v)
+                                                         LaneBits<WPL> Rbb, uint32_t idstk, uint64_t t_start,
+                                                         uint32_t refresh_v)
 {
     const uint32_t (&Rb)[WPL] = Rbb.w;
     const SearchParams& sp = *spp;
@@ -723,14 +719,21 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
     WgHdr* hdr = reinterpret_cast<WgHdr*>(smem);
     uint32_t* lq = smem + kWgHdrWords;
     WaveCtx* ctx = wave_ctx(wl);
-    const uint32_t SW = sp.slot_words, CS = sp.w32cap, RW = sp.rec_words;
-    uint32_t* cur = wl + kWaveFixedWords;
-    uint32_t* stk = cur + SW;
+    const uint32_t SW = sp.slot_words, CS = sp.w32cap, RW = sp.rec_words, SPW = sp.spill_words;
+    uint32_t* stk = wl + kWaveFixedWords;
+    uint32_t* cur = stk + (size_t)sp.lds_depth * SW;
     const uint32_t chunk = bcast0(ctx->spill_chunk);
-    auto frame = [&](uint32_t s) -> uint32_t* {
-        if (s == d) return cur;
-        if (s < sp.lds_depth) return stk + (size_t)s * SW;
-        return sp.spill + ((size_t)chunk * sp.spill_levels + (s - sp.lds_depth)) * SW;
+    // word t (0: P, 1: X, 2: L) of chunk c of frame s, for this lane
+    auto fword = [&](uint32_t s, int c, uint32_t t) -> uint32_t* {
+        const uint32_t li = (uint32_t)c * 64u + lane;
+        if (s == d) return cur + 3u * li + t;
+        if (s < sp.lds_depth) return stk + (size_t)s * SW + 3u * li + t;
+        return sp.spill + ((size_t)chunk * sp.spill_levels + (s - sp.lds_depth)) * SPW + 4u * li + t;
+    };
+    // input id of the child pushed from frame j (j < d)
+    auto child_id = [&](uint32_t j) -> uint32_t {
+        if (j < sp.lds_depth) return rdlane(idstk, j);
+        return bcast0(sp.spill[((size_t)chunk * sp.spill_levels + (j - sp.lds_depth)) * SPW + 3u]);
     };
     if (bcast0(lds_ld(&hdr->done))) return 1;
     const uint32_t busy = bcast0(lds_ld(&hdr->busy));
@@ -757,12 +760,11 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
     bool gave = false;
     if (to_local || asker != 0u) {
         for (uint32_t s = 0; s <= d; s++) {
-            const uint32_t* f = frame(s);
             uint32_t Ls[WPL], Ps[WPL], Xs[WPL], cnt[WPL], incl[WPL];
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
                 const uint32_t w = (uint32_t)c * 64u + lane;
-                Ls[c] = (w < W) ? f[2 * CS + w] : 0u;
+                Ls[c] = (w < W) ? *fword(s, c, 2) : 0u;
             }
             const uint32_t tot = popc_scan<WPL>(Ls, cnt, incl);
             if (tot < 2) continue;
@@ -770,8 +772,8 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
                 const uint32_t w = (uint32_t)c * 64u + lane;
-                Ps[c] = (w < W) ? f[w] : 0u;
-                Xs[c] = (w < W) ? f[CS + w] : 0u;
+                Ps[c] = (w < W) ? *fword(s, c, 0) : 0u;
+                Xs[c] = (w < W) ? *fword(s, c, 1) : 0u;
                 pc += (uint32_t)__builtin_popcount(Ps[c]);
             }
             // frames below are smaller still
@@ -788,7 +790,7 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                 Rs[c] = Rb[c];
             }
             // R of frame s: drop the children pushed from frames s..d-1
-            for (uint32_t j = s; j < d; j++) clear_bit<WPL>(Rs, bcast0(frame(j)[3 * CS]), lane);
+            for (uint32_t j = s; j < d; j++) clear_bit<WPL>(Rs, child_id(j), lane);
             bool ok;
             if (asker != 0u) {
                 // the unit is in transit until the asker takes it: count it
@@ -820,11 +822,10 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                 wg_unlock(hdr, lane);
             }
             if (ok) {
-                uint32_t* fw = frame(s);
 #pragma unroll
                 for (int c = 0; c < WPL; c++) {
                     const uint32_t w = (uint32_t)c * 64u + lane;
-                    if (w < W) fw[2 * CS + w] = L1[c];
+                    if (w < W) *fword(s, c, 2) = L1[c];
                 }
                 if (lane == 0) ctx->donations += 1;
                 gave = true;
@@ -917,6 +918,9 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
 
     const uint32_t me = blockIdx.x;
     uint32_t backoff = 1, idle_iters = 0, polls = 0;
+    LaneAcc acc;
+    acc.x = 0;
+    acc.s = 0;
     for (;;) {
         // ================= obtain a unit =================
         // src 1: the LDS LIFO (slot lsl), 2: the pool of root units (index
@@ -1080,67 +1084,101 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         set_state(kWaveBusy);
 
         // ================= load the unit =================
-        const uint32_t CS = sp.w32cap, SW = sp.slot_words;
-        const uint32_t* rec = (src == 1) ? (lq + (size_t)lsl * RW)
-                            : (src == 2) ? (sp.rec + (size_t)pos * RW)
-                                         : (sp.mail_rec + (size_t)me * RW);
-        const uint32_t g = bcast0(src == 1 ? rec[0] : ld_dev(&rec[0]));
-        const uint32_t W = bcast0(sp.graphs[g].w32);
-        uint32_t Rb[WPL], P[WPL], X[WPL], L[WPL], roff[WPL];
+        const uint32_t CS = sp.w32cap, SW = sp.slot_words, SPW = sp.spill_words;
+        uint32_t Rb[WPL], P[WPL], X[WPL], L[WPL];
+        uint32_t g;
+        if (src == 1) {
+            const uint32_t* rec = lq + (size_t)lsl * RW;
+            g = bcast0(rec[0]);
+            const uint32_t W0 = bcast0(sp.graphs[g].w32);
 #pragma unroll
-        for (int c = 0; c < WPL; c++) {
-            const uint32_t w = (uint32_t)c * 64u + lane;
-            const bool in = w < W;
-            if (src == 1) {
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t w = (uint32_t)c * 64u + lane;
+                const bool in = w < W0;
                 Rb[c] = in ? rec[kRecHeader + w] : 0u;
                 P[c] = in ? rec[kRecHeader + CS + w] : 0u;
                 X[c] = in ? rec[kRecHeader + 2 * CS + w] : 0u;
                 L[c] = in ? rec[kRecHeader + 3 * CS + w] : 0u;
-            } else {
+            }
+            wg_unlock(hdr, lane);
+        } else {
+            const uint32_t* rec = (src == 2) ? (sp.rec + (size_t)pos * RW) : (sp.mail_rec + (size_t)me * RW);
+            g = bcast0(ld_dev(&rec[0]));
+            const uint32_t W0 = bcast0(sp.graphs[g].w32);
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t w = (uint32_t)c * 64u + lane;
+                const bool in = w < W0;
                 Rb[c] = in ? ld_dev(&rec[kRecHeader + w]) : 0u;
                 P[c] = in ? ld_dev(&rec[kRecHeader + CS + w]) : 0u;
                 X[c] = in ? ld_dev(&rec[kRecHeader + 2 * CS + w]) : 0u;
                 L[c] = in ? ld_dev(&rec[kRecHeader + 3 * CS + w]) : 0u;
             }
-            roff[c] = in ? w : (W - 1u);
-        }
-        if (src == 1) {
-            wg_unlock(hdr, lane);
-        } else if (src == 3) {
-            // the record is read: the mailbox may take the next answer
-            vm_drain();
-            if (lane == 0) {
-                st_dev(&sp.mail[me].state, kMailNone);
-                lds_st(&hdr->out, 0u);
+            if (src == 3) {
+                // the record is read: the mailbox may take the next answer
+                vm_drain();
+                if (lane == 0) {
+                    st_dev(&sp.mail[me].state, kMailNone);
+                    lds_st(&hdr->out, 0u);
+                }
             }
         }
         if (g != bcast0(ctx->g)) {
-            cold_fold(spp, wl);
+            cold_fold(spp, wl, acc);
+            acc.x = 0;
+            acc.s = 0;
             if (lane == 0) ctx->g = g;
         }
         if (lane == 0) ctx->units += 1;
 
         // ================= the search of the unit (Alg. 4) =================
         const GraphDesc& gd = sp.graphs[g];
-        const uint32_t* adj = sp.adj + gd.adj_off;
+        const uint32_t W = bcast0(gd.w32);
+        const uint32_t rs4 = 4u * bcast0(gd.rstride);
+        // renumbered rows through a buffer resource: a row is addressed by a
+        // scalar offset (v * row stride) plus this lane's word offset; reads
+        // past the rows return 0
+        const uint64_t abase = reinterpret_cast<uint64_t>(sp.adj + gd.adj_off);
+        const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<void*>(((uint64_t)bcast0((uint32_t)(abase >> 32)) << 32) | bcast0((uint32_t)abase)),
+            (short)0, (int)(bcast0(gd.n) * rs4), 0x00020000);
         const uint32_t* ord = sp.order + gd.ord_off;
         const uint32_t hoff_lo = (uint32_t)gd.hist_off, hoff_hi = (uint32_t)(gd.hist_off >> 32);
+        uint32_t lane_lo[WPL], voff[WPL];
+        bool live[WPL];
+#pragma unroll
+        for (int c = 0; c < WPL; c++) {
+            const uint32_t li = (uint32_t)c * 64u + lane;
+            lane_lo[c] = li << 5;
+            voff[c] = li << 2;
+            live[c] = li < W;
+        }
+        // input id of the vertex whose row is in r: the word after the row
+        auto row_id = [&](const uint32_t (&r)[WPL], uint32_t v) -> uint32_t {
+            if (WPL == 1) return rdlane(r[0], W);
+            if (W < 64u) return rdlane(r[0], W);
+            if (W < 128u) return rdlane(r[WPL - 1], W - 64u);
+            return bcast0(ord[v]);
+        };
+        (void)ord;
         const uint32_t lds_depth = sp.lds_depth;
-        const uint32_t cimask = sp.check_interval - 1u; // check_interval is a power of two
+        const uint32_t ci = sp.check_interval;
         const uint32_t refresh_children = sp.refresh_children;
-        uint32_t* cent = wl + kOffCent;
-        uint16_t* cids = reinterpret_cast<uint16_t*>(wl + kOffCids);
-        uint32_t* cur = wl + kWaveFixedWords;
-        uint32_t* stk = cur + SW;
+        uint32_t* stk = wl + kWaveFixedWords;
+        uint32_t* cur = stk + (size_t)lds_depth * SW;
+        uint32_t* buf = wl + kOffBuf;
+        uint32_t* trash = wl + kOffTrash;
         uint32_t d = 0;          // frames of this unit on the stack
-        uint32_t kids = 0;       // children examined in this unit (low 32 bits)
-        uint32_t nodes = 0;      // nodes created in this unit (low 32 bits)
-        uint32_t nent = 0, used = 0; // clique buffer fill
+        uint32_t budget = ci;    // children until the next check
+        uint32_t kids = 0;       // children examined since the last check
+        uint32_t nodes = 0;      // nodes created since the last check
+        uint32_t nent = 0, used = 0, cent = 0; // clique buffer: cliques, words, lane i: start << 16 | words
+        uint32_t idstk = 0;      // lane j: input id of the child pushed from frame j < lds_depth
         uint32_t chunk = bcast0(ctx->spill_chunk);
         bool abort = false;
 
         for (;;) {
-            int vi = first_bit<WPL>(L);
+            const int vi = first_pos<WPL>(L, lane_lo);
             if (vi < 0) {
                 // node finished: return to the parent frame
                 if (d == 0) break;
@@ -1150,62 +1188,63 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                     const uint32_t* f = stk + (size_t)d * SW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
-                        const uint32_t w = (uint32_t)c * 64u + lane;
-                        const bool in = w < W;
-                        P[c] = in ? f[w] : 0u;
-                        X[c] = in ? f[CS + w] : 0u;
-                        L[c] = in ? f[2 * CS + w] : 0u;
+                        const uint32_t li = (uint32_t)c * 64u + lane;
+                        const uint32_t p0 = f[3 * li], x0 = f[3 * li + 1], l0 = f[3 * li + 2];
+                        P[c] = live[c] ? p0 : 0u;
+                        X[c] = live[c] ? x0 : 0u;
+                        L[c] = live[c] ? l0 : 0u;
                     }
-                    idp = bcast0(f[3 * CS]);
+                    idp = rdlane(idstk, d);
                 } else {
-                    const uint32_t* f = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SW;
+                    const uint32_t* f = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SPW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
-                        const uint32_t w = (uint32_t)c * 64u + lane;
-                        const bool in = w < W;
-                        P[c] = in ? f[w] : 0u;
-                        X[c] = in ? f[CS + w] : 0u;
-                        L[c] = in ? f[2 * CS + w] : 0u;
+                        const uint32_t li = (uint32_t)c * 64u + lane;
+                        P[c] = f[4 * li];
+                        X[c] = f[4 * li + 1];
+                        L[c] = f[4 * li + 2];
                     }
-                    idp = bcast0(f[3 * CS]);
+                    idp = bcast0(f[3]);
                 }
-                clear_bit<WPL>(Rb, idp, lane);
+                uint32_t m[WPL];
+                bit_mask<WPL>(idp, lane_lo, m);
+#pragma unroll
+                for (int c = 0; c < WPL; c++) Rb[c] &= ~m[c];
                 continue;
             }
             const uint32_t v = (uint32_t)vi;
             // step 11: P' = P n N(v), X' = X n N(v)
-            const uint32_t* rv = adj + (size_t)v * W;
+            const uint32_t soff = v * rs4;
             uint32_t row[WPL];
 #pragma unroll
-            for (int c = 0; c < WPL; c++) row[c] = rv[roff[c]];
-            const uint32_t idv = bcast0(ord[v]);
-            clear_bit<WPL>(L, v, lane);
-            uint32_t P2[WPL], X2[WPL];
+            for (int c = 0; c < WPL; c++)
+                row[c] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rows, (int)voff[c], (int)soff, 0);
+            uint32_t m[WPL], P2[WPL], X2[WPL];
+            bit_mask<WPL>(v, lane_lo, m);
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
+                L[c] &= ~m[c];
                 P2[c] = P[c] & row[c];
                 X2[c] = X[c] & row[c];
+                // steps 12-13 for the current node
+                P[c] &= ~m[c];
+                X[c] |= m[c];
             }
-            // steps 12-13 for the current node
-            clear_bit<WPL>(P, v, lane);
-            set_bit<WPL>(X, v, lane);
             kids++;
             if (any_set<WPL>(P2)) {
                 // the child is a node: push the current frame, descend
+                const uint32_t idv = row_id(row, v);
                 nodes++;
-                uint32_t* f;
                 if (d < lds_depth) {
-                    f = stk + (size_t)d * SW;
+                    uint32_t* f = stk + (size_t)d * SW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
-                        const uint32_t w = (uint32_t)c * 64u + lane;
-                        if (w < W) {
-                            f[w] = P[c];
-                            f[CS + w] = X[c];
-                            f[2 * CS + w] = L[c];
-                        }
+                        const uint32_t li = (uint32_t)c * 64u + lane;
+                        f[3 * li] = P[c];
+                        f[3 * li + 1] = X[c];
+                        f[3 * li + 2] = L[c];
                     }
-                    if (lane == 0) f[3 * CS] = idv;
+                    idstk = (lane == d) ? idv : idstk;
                 } else {
                     if (d - lds_depth >= sp.spill_levels) {
                         if (lane == 0) atomicOr(&sp.ctl->error, kErrDepth);
@@ -1224,72 +1263,68 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                         chunk = ch;
                         if (lane == 0) ctx->spill_chunk = ch;
                     }
-                    uint32_t* fs = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SW;
+                    uint32_t* fs = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SPW;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
-                        const uint32_t w = (uint32_t)c * 64u + lane;
-                        if (w < W) {
-                            fs[w] = P[c];
-                            fs[CS + w] = X[c];
-                            fs[2 * CS + w] = L[c];
-                        }
+                        const uint32_t li = (uint32_t)c * 64u + lane;
+                        fs[4 * li] = P[c];
+                        fs[4 * li + 1] = X[c];
+                        fs[4 * li + 2] = L[c];
+                        fs[4 * li + 3] = idv;
                     }
-                    if (lane == 0) {
-                        fs[3 * CS] = idv;
-                        ctx->spills += 1;
-                    }
+                    if (lane == 0) ctx->spills += 1;
                 }
                 d++;
-                set_bit<WPL>(Rb, idv, lane);
+                uint32_t mi[WPL];
+                bit_mask<WPL>(idv, lane_lo, mi);
 #pragma unroll
                 for (int c = 0; c < WPL; c++) {
+                    Rb[c] |= mi[c];
                     P[c] = P2[c];
                     X[c] = X2[c];
                 }
                 // step 9: pivot = first of X if X is non-empty, else first of P
-                int pi = first_bit<WPL>(X);
-                if (pi < 0) pi = first_bit<WPL>(P);
+                int pi = first_pos<WPL>(X, lane_lo);
+                if (pi < 0) pi = first_pos<WPL>(P, lane_lo);
                 // step 10: L = P \ N(p)
-                const uint32_t* rp = adj + (size_t)(uint32_t)pi * W;
+                const uint32_t so = (uint32_t)pi * rs4;
 #pragma unroll
-                for (int c = 0; c < WPL; c++) L[c] = P[c] & ~rp[roff[c]];
+                for (int c = 0; c < WPL; c++)
+                    L[c] = P[c] & ~(uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rows, (int)voff[c], (int)so, 0);
             } else if (!any_set<WPL>(X2)) {
                 // P' and X' empty: R u {v} is maximal.  R is the bitset Rb over
-                // input ids, so the clique's sorted ids are its set bits in
-                // lane order.
-                uint32_t cw[WPL], cnt[WPL], incl[WPL];
-                const uint32_t iw = idv >> 5, im = 1u << (idv & 31);
-#pragma unroll
-                for (int c = 0; c < WPL; c++) cw[c] = Rb[c] | (((uint32_t)c * 64u + lane == iw) ? im : 0u);
-                const uint32_t k = popc_scan<WPL>(cw, cnt, incl);
-                if (k > kCliqueIds) {
-                    LaneBits<WPL> cwb;
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) cwb.w[c] = cw[c];
-                    cold_big_clique<WPL>(spp, wl, cwb, hoff_lo, hoff_hi);
-                } else {
-                    if (nent == kCliqueEntries || used + k > kCliqueIds) {
-                        cold_flush(spp, wl, nent, used, hoff_lo, hoff_hi);
-                        nent = 0;
-                        used = 0;
-                    }
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) {
-                        uint32_t p = used + incl[c] - cnt[c];
-                        uint32_t x = cw[c];
-                        const uint32_t wb = ((uint32_t)c * 64u + lane) << 5;
-                        while (x) {
-                            cids[p++] = (uint16_t)(wb | (uint32_t)__builtin_ctz(x));
-                            x &= x - 1;
-                        }
-                    }
-                    if (lane == 0) cent[nent] = used | (k << 16);
-                    used += k;
-                    nent++;
+                // input ids; its non-empty 16-bit halves, in lane order, are the
+                // clique's sorted ids.
+                const uint32_t idv = row_id(row, v);
+                if (nent == 64u || used + 2u * 64u * WPL > kCliqueSlots) {
+                    acc = cold_flush(spp, wl, cent, nent, hoff_lo, hoff_hi, acc);
+                    nent = 0;
+                    used = 0;
                 }
+                uint32_t mi[WPL];
+                bit_mask<WPL>(idv, lane_lo, mi);
+                const uint32_t start = used;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    const uint32_t cw = Rb[c] | mi[c];
+                    const uint32_t lo = cw & 0xffffu, hi = cw >> 16;
+                    const uint64_t blo = ballot(lo != 0u), bhi = ballot(hi != 0u);
+                    const uint32_t below =
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(blo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)blo, 0u)) +
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(bhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bhi, 0u));
+                    const uint32_t plo = used + below;
+                    const uint32_t phi = plo + (lo != 0u ? 1u : 0u);
+                    const uint32_t hw = (((uint32_t)c * 64u + lane) << 1);
+                    *(lo != 0u ? buf + plo : trash + lane) = (hw << 16) | lo;
+                    *(hi != 0u ? buf + phi : trash + lane) = ((hw + 1u) << 16) | hi;
+                    used += (uint32_t)__builtin_popcountll(blo) + (uint32_t)__builtin_popcountll(bhi);
+                }
+                cent = (lane == nent) ? ((start << 16) | (used - start)) : cent;
+                nent++;
             }
 
-            if ((kids & cimask) == 0u) {
+            if (--budget == 0u) {
+                budget = ci;
                 // Look at the siblings (LDS only); call the out-of-line handler
                 // only when there is something to do.
                 if (lane == 0) {
@@ -1306,10 +1341,9 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 const uint32_t asked = bcast0(lds_ld(&hdr->req));
                 uint32_t tk = 0;
                 if (lane == 0)
-                    tk = __hip_atomic_fetch_add(&hdr->ticks, cimask + 1u, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+                    tk = __hip_atomic_fetch_add(&hdr->ticks, ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 tk = bcast0(tk);
-                const uint32_t refresh = (tk / refresh_children) != ((tk + cimask + 1u) / refresh_children);
+                const uint32_t refresh = (tk / refresh_children) != ((tk + ci) / refresh_children);
                 if (dn) {
                     abort = true;
                     break;
@@ -1317,24 +1351,23 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 if (refresh || asked || lqn == 0u || (lqn < kLocalSlots && NW - busy > lqn)) {
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
-                        const uint32_t w = (uint32_t)c * 64u + lane;
-                        if (w < W) {
-                            cur[w] = P[c];
-                            cur[CS + w] = X[c];
-                            cur[2 * CS + w] = L[c];
-                        }
+                        const uint32_t li = (uint32_t)c * 64u + lane;
+                        cur[3 * li] = P[c];
+                        cur[3 * li + 1] = X[c];
+                        cur[3 * li + 2] = L[c];
                     }
                     LaneBits<WPL> rbb;
 #pragma unroll
                     for (int c = 0; c < WPL; c++) rbb.w[c] = Rb[c];
-                    if (bcast0(cold_check<WPL>(spp, smem, wl, d, W, g, rbb, t_start, refresh))) {
+                    if (bcast0(cold_check<WPL>(spp, smem, wl, d, W, g, rbb, idstk, t_start, refresh))) {
                         abort = true;
                         break;
                     }
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
-                        const uint32_t w = (uint32_t)c * 64u + lane;
-                        L[c] = (w < W) ? cur[2 * CS + w] : 0u;
+                        const uint32_t li = (uint32_t)c * 64u + lane;
+                        const uint32_t l0 = cur[3 * li + 2];
+                        L[c] = live[c] ? l0 : 0u;
                     }
                     chunk = bcast0(ctx->spill_chunk);
                 }
@@ -1342,7 +1375,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         }
 
         // ---- unit finished ----
-        if (nent) cold_flush(spp, wl, nent, used, hoff_lo, hoff_hi);
+        if (nent) acc = cold_flush(spp, wl, cent, nent, hoff_lo, hoff_hi, acc);
         if (lane == 0) {
             ctx->nodes += nodes;
             ctx->children += kids;
@@ -1357,7 +1390,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         wg_unlock(hdr, lane);
         if (abort) break;
     }
-    cold_fold(spp, wl);
+    cold_fold(spp, wl, acc);
     set_state(kWaveExited);
     if (lane == 0) {
         if (ctx->units) atomicAdd(&sp.ctl->units, ctx->units);
@@ -1373,6 +1406,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
 hipError_t launch_validate(const uint64_t* rows, uint32_t n, uint32_t rw, unsigned int* flag,
                            hipStream_t s)
 {
+    (void)hipGetLastError(); // report only this call's launch errors
     const uint64_t total = (uint64_t)n * rw;
     if (total == 0) return hipSuccess;
     const uint32_t blocks = (uint32_t)((total + 255) / 256);
@@ -1383,6 +1417,7 @@ hipError_t launch_validate(const uint64_t* rows, uint32_t n, uint32_t rw, unsign
 hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
                         const uint64_t* rows_in, uint32_t* order, hipStream_t s)
 {
+    (void)hipGetLastError(); // report only this call's launch errors
     if (max_n <= 512)
         hipLaunchKernelGGL(order_kernel<8>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
     else if (max_n <= 1024)
@@ -1398,6 +1433,7 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
                           const uint64_t* rows_in, const uint32_t* order, uint32_t* adj,
                           hipStream_t s)
 {
+    (void)hipGetLastError(); // report only this call's launch errors
     if (max_n == 0) return hipSuccess;
     hipLaunchKernelGGL(relabel_kernel, dim3(max_n, num_graphs), dim3(64), 0, s, graphs, rows_in,
                        order, adj);
@@ -1407,6 +1443,7 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
                         uint32_t workgroups, hipStream_t s)
 {
+    (void)hipGetLastError(); // report only this call's launch errors
     uint64_t work = hist_total;
     if (work < (uint64_t)workgroups * (sizeof(Mailbox) / 4)) work = (uint64_t)workgroups * (sizeof(Mailbox) / 4);
     if (work < (uint64_t)num_graphs * 8) work = (uint64_t)num_graphs * 8;
@@ -1420,6 +1457,7 @@ hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hi
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
                        uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s)
 {
+    (void)hipGetLastError(); // report only this call's launch errors
     // writers per graph: enough to fill the queue quickly, few per graph in a batch
     uint32_t k = 1;
     while (k < 64 && k < max_units && (uint64_t)num_graphs * k < 4096) k <<= 1;
@@ -1453,10 +1491,11 @@ static hipError_t ensure_search_attr()
 hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s)
 {
+    (void)hipGetLastError(); // report only this call's launch errors
     const uint32_t lds = search_lds_bytes(sp.wave_lds_words, sp.rec_words, waves_per_block);
     hipError_t e = ensure_search_attr();
     if (e != hipSuccess) return e;
-    if (max_w32 <= 64)
+    if (search_chunks(max_w32) == 1)
         hipLaunchKernelGGL(search_kernel<1>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp, d_sp);
     else
         hipLaunchKernelGGL(search_kernel<2>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp, d_sp);
@@ -1466,7 +1505,7 @@ hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint3
 hipError_t search_occupancy(uint32_t max_w32, uint32_t waves_per_block, uint32_t lds_bytes,
                             int* blocks_per_cu)
 {
-    const void* k = (max_w32 <= 64) ? (const void*)search_kernel<1> : (const void*)search_kernel<2>;
+    const void* k = search_chunks(max_w32) == 1 ? (const void*)search_kernel<1> : (const void*)search_kernel<2>;
     hipError_t e = ensure_search_attr();
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, (int)(64 * waves_per_block),

@@ -8,10 +8,10 @@
 namespace mce {
 
 constexpr uint32_t kMaxN = 4096;
-// Per-wavefront clique buffer in LDS: sorted input ids (u16) of cliques waiting
-// to be hashed, and one entry word (start | size << 16) per clique.
-constexpr uint32_t kCliqueIds = 512;
-constexpr uint32_t kCliqueEntries = 64;
+// Per-wavefront clique buffer in LDS: each buffered clique is the list of the
+// non-empty 16-bit halves of its input-id bitset, one word per half
+// (half index << 16 | bits), in increasing order; at most 64 cliques.
+constexpr uint32_t kCliqueSlots = 512;
 // Per-wavefront LDS histogram; larger clique sizes go straight to HBM.
 constexpr uint32_t kHistLds = 64;
 // Words at the head of a queue record (graph index, spare).
@@ -19,20 +19,38 @@ constexpr uint32_t kRecHeader = 2;
 // Per-workgroup LDS: a header and a LIFO of units shared by its wavefronts.
 constexpr uint32_t kWgHdrWords = 16;
 constexpr uint32_t kLocalSlots = 8;
-// LDS words of a wavefront before its frames: histogram (kHistLds u64), per-lane
-// hash accumulators (2 x 64 u64), clique buffer entries (kCliqueEntries u32) and
-// ids (kCliqueIds u16), and a 32-word context block.  Then come the slot of the
-// current frame and the stack window.
-constexpr uint32_t kWaveFixedWords = kHistLds * 2 + 256 + kCliqueEntries + kCliqueIds / 2 + 32;
+// LDS words of a wavefront before its frames: histogram (kHistLds u64), the
+// clique buffer (kCliqueSlots words), 64 words that absorb the stores of lanes
+// with nothing to store, and a 32-word context block.  Then come the stack
+// window, the slot of the current frame and some slack (lds_frame_words).
+constexpr uint32_t kWaveFixedWords = kHistLds * 2 + kCliqueSlots + 64 + 32;
+
+// Wavefront-lane layout of the search: one 32-bit word per lane and chunk.
+// A graph with w32 + 1 <= 64 row words (n <= 2016) uses one chunk, larger ones
+// two (the +1 is the input-id word of a row).
+constexpr uint32_t kOneChunkMaxW32 = 63;
+inline uint32_t search_chunks(uint32_t max_w32) { return max_w32 <= kOneChunkMaxW32 ? 1u : 2u; }
+
+// LDS stack frame (P, X, L interleaved per lane, 12 bytes a lane): words per
+// frame, and the slack after the last frame that absorbs the stores of lanes
+// past the row.
+inline uint32_t lds_frame_words(uint32_t max_w32) { return search_chunks(max_w32) == 1 ? 3u * max_w32 : 384u; }
+inline uint32_t lds_slack_words(uint32_t max_w32)
+{
+    return search_chunks(max_w32) == 1 ? 3u * (64u - max_w32) : 0u;
+}
+// Spill frame in HBM: (P, X, L, child id) per lane, 16 bytes a lane, all lanes.
+inline uint32_t spill_frame_words(uint32_t max_w32) { return 256u * search_chunks(max_w32); }
 
 // One graph of a handle, in device memory.
 struct GraphDesc {
     uint32_t n;        // vertices
     uint32_t w32;      // 32-bit words of a bitset, ceil(n/32)
     uint32_t rw64;     // uint64 words of an input row, ceil(n/64)
-    uint32_t pad;
+    uint32_t rstride;  // uint32 words between renumbered rows: w32 + 1 (the last word of a
+                       // row holds the vertex's input id)
     uint64_t in_off;   // first uint64 word of the input rows
-    uint64_t adj_off;  // first uint32 word of the renumbered rows (row stride w32)
+    uint64_t adj_off;  // first uint32 word of the renumbered rows (row stride rstride)
     uint64_t ord_off;  // first entry of order[] (position -> input id)
     uint64_t hist_off; // first entry of the graph's histogram (n + 1 entries)
 };
@@ -93,7 +111,8 @@ struct SearchParams {
     uint32_t num_wg;          // search workgroups
     uint32_t rec_words;       // kRecHeader + 4 * w32cap
     uint32_t w32cap;          // bitset stride in LDS slots and records
-    uint32_t slot_words;      // 3 * w32cap + 1
+    uint32_t slot_words;      // LDS frame stride (lds_frame_words)
+    uint32_t spill_words;     // spill frame stride (spill_frame_words)
     uint32_t lds_depth;       // stack levels in LDS
     uint32_t spill_levels;    // stack levels in one spill chunk
     uint32_t spill_chunks;    // chunks in the spill pool

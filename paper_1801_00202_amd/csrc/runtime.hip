@@ -327,12 +327,13 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     LaunchCfg c;
     c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16) : 8u;
     c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
-    c.slot_words = 3 * c.w32cap + 1;
+    c.slot_words = lds_frame_words(c.w32cap);
+    const uint32_t slack = lds_slack_words(c.w32cap);
     uint32_t depth = o.lds_depth >= 0 ? (uint32_t)std::min<int64_t>(o.lds_depth, 64) : 12u;
     // keep a workgroup within the LDS limit
     const uint32_t rec_words = kRecHeader + 4 * c.w32cap;
     for (;;) {
-        uint32_t wl = kWaveFixedWords + (depth + 1) * c.slot_words;
+        uint32_t wl = kWaveFixedWords + (depth + 1) * c.slot_words + slack;
         wl = (wl + 1u) & ~1u;
         if (search_lds_bytes(wl, rec_words, c.wpb) <= di.lds_per_block || (depth == 0 && c.wpb == 1)) {
             c.wave_lds_words = wl;
@@ -376,7 +377,7 @@ int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
     if ((rc = h->d_rec.ensure(4ull * rec_words * c.cap)) != MCE_OK) return rc;
     if ((rc = h->d_mail.ensure(sizeof(Mailbox) * (uint64_t)c.blocks)) != MCE_OK) return rc;
     if ((rc = h->d_mail_rec.ensure(4ull * rec_words * c.blocks)) != MCE_OK) return rc;
-    const uint64_t spill = 4ull * c.slot_words * c.spill_levels * c.spill_chunks;
+    const uint64_t spill = 4ull * spill_frame_words(c.w32cap) * c.spill_levels * c.spill_chunks;
     if ((rc = h->d_spill.ensure(spill)) != MCE_OK) return rc;
     if ((rc = h->d_state.ensure(4ull * c.blocks * c.wpb)) != MCE_OK) return rc;
     if ((rc = h->d_params.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
@@ -404,6 +405,7 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
     sp.rec_words = kRecHeader + 4 * c.w32cap;
     sp.w32cap = c.w32cap;
     sp.slot_words = c.slot_words;
+    sp.spill_words = spill_frame_words(c.w32cap);
     sp.lds_depth = c.lds_depth;
     sp.spill_levels = c.spill_levels;
     sp.spill_chunks = c.spill_chunks;
@@ -536,8 +538,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
                 hipGraph_t graph = nullptr;
                 hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    // the events around the search kernel become nodes of the graph
-                    rc = enqueue_solve(g, c, sp, first, last, cs, true);
+                    rc = enqueue_solve(g, c, sp, first, last, cs, false);
                     e = hipStreamEndCapture(cs, &graph);
                 }
                 (void)hipStreamDestroy(cs);
@@ -584,7 +585,11 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         mce_stats_t st;
         std::memset(&st, 0, sizeof(st));
         if (hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess) st.search_us = ms * 1000.0;
-        if (hipEventElapsedTime(&ms, g->ev[2], g->ev[3]) == hipSuccess) st.search_kernel_us = ms * 1000.0;
+        // a replayed graph carries no events around the search kernel
+        const bool replayed = use_graph && !enumerate && first == 0 && last == UINT64_MAX;
+        if (!replayed && hipEventElapsedTime(&ms, g->ev[2], g->ev[3]) == hipSuccess)
+            st.search_kernel_us = ms * 1000.0;
+        (void)hipGetLastError(); // a failed timing query must not surface in a later launch check
         st.prepare_us = g->prepare_ms * 1000.0;
         st.blocks = c.blocks;
         st.waves_per_block = c.wpb;
@@ -716,6 +721,7 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
         std::memset(&gd, 0, sizeof(gd));
         gd.n = n;
         gd.w32 = (n + 31) / 32;
+        gd.rstride = gd.w32 + 1;
         gd.rw64 = n ? row_words : 0;
         gd.in_off = 0;
         desc.push_back(gd);
@@ -735,6 +741,7 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
             std::memset(&gd, 0, sizeof(gd));
             gd.n = ni;
             gd.w32 = (ni + 31) / 32;
+            gd.rstride = gd.w32 + 1;
             gd.rw64 = (ni + 63) / 64;
             gd.in_off = batch->row_offset_words[i];
             if (ni && gd.in_off + (uint64_t)ni * gd.rw64 > (uint64_t)row_words) return MCE_E_INVAL;
@@ -761,7 +768,7 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
         gd.adj_off = adj;
         gd.ord_off = ord;
         gd.hist_off = hist;
-        adj += (uint64_t)gd.n * gd.w32;
+        adj += (uint64_t)gd.n * gd.rstride;
         ord += gd.n;
         hist += gd.n + 1;
         h->max_n = std::max(h->max_n, gd.n);
@@ -774,7 +781,8 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
     h->hist_total = hist;
     if ((rc = h->d_desc.ensure(sizeof(GraphDesc) * desc.size())) != MCE_OK) return rc;
     if ((rc = h->d_in.ensure(8 * std::max<uint64_t>(in_words, 1))) != MCE_OK) return rc;
-    if ((rc = h->d_adj.ensure(4 * std::max<uint64_t>(adj, 1))) != MCE_OK) return rc;
+    // 128 words of padding: a row load reads up to 128 words from the row start
+    if ((rc = h->d_adj.ensure(4 * (adj + 128))) != MCE_OK) return rc;
     if ((rc = h->d_order.ensure(4 * std::max<uint64_t>(ord, 1))) != MCE_OK) return rc;
     if ((rc = ensure_events(h.get())) != MCE_OK) return rc;
     HIP_TRY(hipEventRecord(h->ev[0], s));
@@ -980,7 +988,8 @@ uint64_t job_footprint(mce_graph_s* h)
     if (make_cfg(h, &c, 0) != MCE_OK) return 0;
     const uint64_t rec_words = kRecHeader + 4ull * c.w32cap;
     return sizeof(DevResult) * h->num_graphs + 8ull * h->hist_total + 4ull * c.cap * rec_words +
-           (sizeof(Mailbox) + 4ull * rec_words) * c.blocks + 4ull * c.slot_words * c.spill_levels * c.spill_chunks;
+           (sizeof(Mailbox) + 4ull * rec_words) * c.blocks +
+           4ull * spill_frame_words(c.w32cap) * c.spill_levels * c.spill_chunks;
 }
 
 void worker_loop(uint32_t slot)

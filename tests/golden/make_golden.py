@@ -1,0 +1,77 @@
+"""Write the expected results of the full-size workloads with the CPU oracle.
+
+Calls only ``oracle`` (and ``synth`` for the seeded inputs).  Usage, from the
+repository root:
+
+    python tests/golden/make_golden.py [--threads T] [--only NAME ...]
+
+Outputs (next to this script):
+  full_configs.json   G(1000, 0.3) seed 0; Moon-Moser k = 15 and a relabelled
+                      copy; planted G(800, 0.5) seed 0 (12 cliques of 20..40)
+  batch4096_seed0.csv the 4096-graph batch (base seed 0), one line per graph
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+MM_PERM_SEED = 1
+
+
+def full_configs(threads):
+    out = {}
+    cases = {
+        "gnp1000_p0.3_s0": lambda: synth.gnp(1000, 0.3, 0),
+        "moon_moser_15": lambda: synth.moon_moser(15),
+        "moon_moser_15_relabelled": lambda: synth.relabel(
+            synth.moon_moser(15), np.random.Generator(np.random.PCG64(MM_PERM_SEED)).permutation(45)),
+        "planted800_p0.5_s0": lambda: synth.gnp_planted(800, 0.5, 0)[0],
+    }
+    for name, make in cases.items():
+        t0 = time.perf_counter()
+        rows = make()
+        r = oracle.greedy(rows, threads=threads)
+        r["root_branches"] = oracle.root_branches(rows)
+        r["oracle_seconds"] = round(time.perf_counter() - t0, 2)
+        r["oracle_threads"] = threads
+        out[name] = r
+        print(name, r["count"], r["nodes"], r["oracle_seconds"], flush=True)
+    return out
+
+
+def batch(threads):
+    specs = synth.batch_mix(4096, 0)
+    lines = ["index,n,p,seed,count,nodes,children,dead_ends,hash_xor,hash_sum,omega"]
+    t0 = time.perf_counter()
+    for i, (n, p, seed) in enumerate(specs):
+        r = oracle.greedy(synth.gnp(n, p, seed), threads=threads)
+        lines.append("%d,%d,%r,%d,%d,%d,%d,%d,%d,%d,%d" % (i, n, p, seed, r["count"], r["nodes"], r["children"],
+                                                        r["dead_ends"], r["hash_xor"], r["hash_sum"], r["omega"]))
+    print("batch", len(specs), round(time.perf_counter() - t0, 1), "s", flush=True)
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--only", nargs="*", default=["full", "batch"])
+    a = ap.parse_args()
+    if "full" in a.only:
+        with open(os.path.join(HERE, "full_configs.json"), "w") as f:
+            json.dump(full_configs(a.threads), f, indent=1, sort_keys=True)
+    if "batch" in a.only:
+        with open(os.path.join(HERE, "batch4096_seed0.csv"), "w") as f:
+            f.write(batch(a.threads))
+
+
+if __name__ == "__main__":
+    main()
