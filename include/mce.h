@@ -152,6 +152,21 @@ int mce_count_range(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t *
                     void *hip_stream);
 
 /*
+ * mce_count_subproblem -- single-graph handles only: the search below one node
+ * of Alg. 4, (R, P, X), given as lists of positions of the ordering
+ * (mce_get_order: position i is input id order[i]).  R is the clique so far,
+ * P the candidates, X the excluded vertices; the three lists must be disjoint
+ * and P non-empty.  The node's pivot and branch set follow Alg. 4 (pivot: the
+ * first vertex of X, else of P; L = P \ N(p)), the node counts as one search
+ * node, and the results cover the maximal cliques R u K found below it, hashed
+ * on input ids like every result.  Host arrays, copied before the call
+ * returns.  Errors: MCE_E_INVAL (NULL, empty P, a position >= n, overlapping
+ * lists, a batch handle), MCE_E_NOMEM, MCE_E_DEVICE.
+ */
+int mce_count_subproblem(mce_graph_t g, const uint32_t *R, uint32_t nr, const uint32_t *P, uint32_t np,
+                         const uint32_t *X, uint32_t nx, mce_result_t *res, void *hip_stream);
+
+/*
  * mce_enumerate -- single-graph handles only: like mce_count, and also writes
  * every maximal clique as its sorted input ids.
  *   verts: device array of verts_cap uint32; offsets: device array of

@@ -84,7 +84,7 @@ def _load():
         lib.orc_greedy_range_mt.argtypes = [u32, p64, u32, u64, u64, i32, pres]
         lib.orc_root_branches.argtypes = [u32, p64, u32, p64]
         lib.orc_greedy_list.argtypes = [u32, p64, u32, pres, p32, u64, p64, u64, p64, p64]
-        lib.orc_subproblem.argtypes = [u32, p64, u32, i32, p32, u32, p32, u32, p32, u32, pres]
+        lib.orc_subproblem.argtypes = [u32, p64, u32, i32, p32, p32, u32, p32, u32, p32, u32, pres]
         for name in ("orc_order", "orc_greedy", "orc_tomita", "orc_brute", "orc_greedy_range",
                      "orc_greedy_mt", "orc_greedy_range_mt", "orc_root_branches",
                      "orc_greedy_list", "orc_subproblem"):
@@ -215,14 +215,22 @@ def greedy_list(rows) -> tuple[dict, list[tuple[int, ...]]]:
     return _to_dict(r, hist), cliques
 
 
-def subproblem(rows, R, P, X, mode: str = "greedy") -> dict:
-    """One (R, P, X) subproblem with labels taken as positions of the ordering."""
+def subproblem(rows, R, P, X, mode: str = "greedy", ids=None) -> dict:
+    """One (R, P, X) subproblem with labels taken as positions of the ordering
+    (rows given in that numbering).  ids[label] is the id a clique member is
+    reported (and hashed) as; None keeps the labels."""
     rows, n, rw = _rows(rows)
     m = {"greedy": 0, "tomita": 1}[mode]
     Ra = np.ascontiguousarray(list(R) or [0], dtype=np.uint32)
     Pa = np.ascontiguousarray(list(P) or [0], dtype=np.uint32)
     Xa = np.ascontiguousarray(list(X) or [0], dtype=np.uint32)
+    ida = None
+    if ids is not None:
+        ida = np.ascontiguousarray(ids, dtype=np.uint32)
+        if ida.shape != (n,):
+            raise ValueError("ids must have one entry per vertex")
     r, hist = _new_result(n)
-    _check(_load().orc_subproblem(n, _ptr64(rows), rw, m, _ptr32(Ra), len(R), _ptr32(Pa), len(P),
-                                  _ptr32(Xa), len(X), ctypes.byref(r)))
+    _check(_load().orc_subproblem(n, _ptr64(rows), rw, m, None if ida is None else _ptr32(ida),
+                                  _ptr32(Ra), len(R), _ptr32(Pa), len(P), _ptr32(Xa), len(X),
+                                  ctypes.byref(r)))
     return _to_dict(r, hist)

@@ -592,11 +592,13 @@ int orc_tomita(uint32_t n, const uint64_t *rows, uint32_t row_words, orc_result 
     return solve_range(n, rows, row_words, 1, 1, 0, UINT64_MAX, &out);
 }
 
-/* One subproblem (R, P, X) of a graph whose input labels are taken as the
- * positions of the ordering (no reordering).  R, P, X are lists of labels;
- * P and X need not be sorted.  The subproblem root is counted as a node when P
- * is non-empty.  mode 0: GreedyBB pivot, 1: Tomita pivot. */
-int orc_subproblem(uint32_t n, const uint64_t *rows, uint32_t row_words, int mode,
+/* One subproblem (R, P, X) of a graph whose labels are taken as the positions
+ * of the ordering (no reordering).  R, P, X are lists of labels; P and X need
+ * not be sorted.  The subproblem root is counted as a node when P is
+ * non-empty.  mode 0: GreedyBB pivot, 1: Tomita pivot.  ids (may be NULL: the
+ * labels themselves) gives the id reported for each label: cliques are mapped
+ * through it and sorted before they are hashed. */
+int orc_subproblem(uint32_t n, const uint64_t *rows, uint32_t row_words, int mode, const uint32_t *ids,
                    const uint32_t *R, uint32_t nr, const uint32_t *P, uint32_t np,
                    const uint32_t *X, uint32_t nx, orc_result *res)
 {
@@ -613,7 +615,7 @@ int orc_subproblem(uint32_t n, const uint64_t *rows, uint32_t row_words, int mod
     memset(&pp, 0, sizeof(pp));
     pp.pg = g;
     pp.order = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
-    for (uint32_t i = 0; i < n; i++) pp.order[i] = i;
+    for (uint32_t i = 0; i < n; i++) pp.order[i] = ids ? ids[i] : i;
     sink out;
     sink_init(&out, res);
     search s;
@@ -631,7 +633,7 @@ int orc_subproblem(uint32_t n, const uint64_t *rows, uint32_t row_words, int mod
             node(&s, Pw, npw, Xw, nxw);
         } else if (!nxw) {
             /* R itself is maximal */
-            for (uint32_t i = 0; i < nr; i++) s.report_buf[i] = R[i];
+            for (uint32_t i = 0; i < nr; i++) s.report_buf[i] = pp.order[R[i]];
             sink_report(&out, s.report_buf, nr);
         }
     } else {

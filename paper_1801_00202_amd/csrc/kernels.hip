@@ -471,6 +471,62 @@ __global__ void __launch_bounds__(64) root_units_kernel(SearchParams sp, uint64_
     }
 }
 
+// One node (R, P, X) of graph 0, given as position bitsets (w32 words each,
+// R then P then X), as the only unit of the pool: R is mapped to input ids,
+// the node's pivot (first of X, else first of P) and L = P \ N(p) are taken
+// as in Alg. 4, and the node itself is counted.  One wavefront.  P must not be
+// empty (the host checks).
+template <int WPL>
+__global__ void __launch_bounds__(64) subproblem_kernel(SearchParams sp, const uint32_t* bits)
+{
+    const GraphDesc gd = sp.graphs[0];
+    const uint32_t W = gd.w32, lane = lane_id(), cs = sp.w32cap;
+    const uint32_t* ord = sp.order + gd.ord_off;
+    const uint32_t* adj = sp.adj + gd.adj_off;
+    uint32_t Rp[WPL], P[WPL], X[WPL], Rb[WPL], L[WPL], cnt[WPL], incl[WPL];
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t w = (uint32_t)c * 64u + lane;
+        const bool in = w < W;
+        Rp[c] = in ? bits[w] : 0u;
+        P[c] = in ? bits[W + w] : 0u;
+        X[c] = in ? bits[2 * W + w] : 0u;
+        Rb[c] = 0u;
+    }
+    for (int q = first_bit<WPL>(Rp); q >= 0; q = first_bit<WPL>(Rp)) {
+        clear_bit<WPL>(Rp, (uint32_t)q, lane);
+        set_bit<WPL>(Rb, bcast0(ord[q]), lane);
+    }
+    int p = first_bit<WPL>(X);
+    if (p < 0) p = first_bit<WPL>(P);
+    if (p < 0) return;
+    const uint32_t* rp = adj + (size_t)(uint32_t)p * gd.rstride;
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t w = (uint32_t)c * 64u + lane;
+        L[c] = (w < W) ? (P[c] & ~rp[w]) : 0u;
+    }
+    const uint32_t total = popc_scan<WPL>(L, cnt, incl);
+    uint32_t* rec = sp.rec;
+    if (lane == 0) {
+        rec[0] = 0u;
+        sp.results[0].root_branches = total;
+        sp.results[0].nodes += 1ull;
+        sp.ctl->pool_size = 1u;
+        sp.ctl->work = 1u;
+    }
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t w = (uint32_t)c * 64u + lane;
+        if (w < W) {
+            rec[kRecHeader + w] = Rb[c];
+            rec[kRecHeader + cs + w] = P[c];
+            rec[kRecHeader + 2 * cs + w] = X[c];
+            rec[kRecHeader + 3 * cs + w] = L[c];
+        }
+    }
+}
+
 // ------------------------------------------------------ the search -------
 //
 // Scheduling is two-level, so that no HBM word is polled by every workgroup:
@@ -1468,6 +1524,16 @@ hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max
         hipLaunchKernelGGL(root_plan_kernel<2>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
         hipLaunchKernelGGL(root_units_kernel<2>, dim3(num_graphs, k), dim3(64), 0, s, sp, first, last);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uint32_t* bits, hipStream_t s)
+{
+    (void)hipGetLastError(); // report only this call's launch errors
+    if (max_w32 <= 64)
+        hipLaunchKernelGGL(subproblem_kernel<1>, dim3(1), dim3(64), 0, s, sp, bits);
+    else
+        hipLaunchKernelGGL(subproblem_kernel<2>, dim3(1), dim3(64), 0, s, sp, bits);
     return hipGetLastError();
 }
 

@@ -146,6 +146,7 @@ hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hi
                         uint32_t workgroups, hipStream_t s);
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
                        uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s);
+hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uint32_t* bits, hipStream_t s);
 hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s);
 hipError_t search_occupancy(uint32_t max_w32, uint32_t waves_per_block, uint32_t lds_bytes,

@@ -293,7 +293,7 @@ struct mce_graph_s {
     uint64_t in_words = 0, adj_words = 0, ord_words = 0, hist_total = 0;
     DevBuf d_desc, d_in, d_adj, d_order;
     // workspace of the solve
-    DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params;
+    DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params, d_sub;
     HostPinned h_params; // staging of the search parameters (stable for graph replays)
     HostPinned h_out; // results | ctl | hist, copied back in one go
     LaunchCfg cfg;
@@ -426,12 +426,17 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
 
 // The solve sequence on a stream: reset, root, search, copy-out.
 int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, uint64_t first,
-                  uint64_t last, hipStream_t s, bool timed)
+                  uint64_t last, hipStream_t s, bool timed, const uint32_t* sub_bits = nullptr)
 {
     HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.blocks, s));
-    // the root children of all graphs fill at most the pool
-    const uint32_t max_units = std::max<uint32_t>(1u, c.cap / h->num_graphs);
-    HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, max_units, s));
+    if (sub_bits) {
+        // one given node of graph 0 instead of the root
+        HIP_TRY(launch_subproblem(sp, h->max_w32, sub_bits, s));
+    } else {
+        // the root children of all graphs fill at most the pool
+        const uint32_t max_units = std::max<uint32_t>(1u, c.cap / h->num_graphs);
+        HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, max_units, s));
+    }
     std::memcpy(h->h_params.p, &sp, sizeof(sp));
     HIP_TRY(hipMemcpyAsync(h->d_params.p, h->h_params.p, sizeof(sp), hipMemcpyHostToDevice, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
@@ -506,7 +511,7 @@ int ensure_events(mce_graph_s* h)
 // Run one solve (count, count_range or enumerate) synchronously.
 int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, hipStream_t s,
               uint32_t* verts, uint64_t verts_cap, uint64_t* offs, uint64_t offs_cap,
-              QueueCtl* ctl_out, bool use_graph, uint32_t blocks_cap = 0)
+              QueueCtl* ctl_out, bool use_graph, uint32_t blocks_cap = 0, const uint32_t* sub_bits = nullptr)
 {
     int rc = ensure_events(g);
     if (rc != MCE_OK) return rc;
@@ -556,7 +561,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
             }
             HIP_TRY(hipGraphLaunch(g->graph_exec, s));
         } else {
-            if ((rc = enqueue_solve(g, c, sp, first, last, s, true)) != MCE_OK) return rc;
+            if ((rc = enqueue_solve(g, c, sp, first, last, s, true, sub_bits)) != MCE_OK) return rc;
         }
         HIP_TRY(hipEventRecord(g->ev[1], s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -874,6 +879,35 @@ int mce_count_range(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* 
     if (rc != MCE_OK) return rc;
     rc = run_solve(g, first, last, res, static_cast<hipStream_t>(hip_stream), nullptr, 0, nullptr, 0,
                    nullptr, false);
+    if (rc != MCE_OK) res->status = rc;
+    return rc;
+}
+
+int mce_count_subproblem(mce_graph_t g, const uint32_t* R, uint32_t nr, const uint32_t* P, uint32_t np,
+                         const uint32_t* X, uint32_t nx, mce_result_t* res, void* hip_stream)
+{
+    if (!g || !res || g->num_graphs != 1 || np == 0 || !P || (nr && !R) || (nx && !X)) return MCE_E_INVAL;
+    const uint32_t n = g->desc[0].n, w32 = g->desc[0].w32;
+    // position bitsets R, P, X; the three sets must be disjoint
+    std::vector<uint32_t> bits(3ull * w32, 0u);
+    auto add = [&](const uint32_t* list, uint32_t len, uint32_t which) -> bool {
+        for (uint32_t i = 0; i < len; i++) {
+            const uint32_t v = list[i];
+            if (v >= n) return false;
+            for (uint32_t t = 0; t < 3; t++)
+                if (bits[(size_t)t * w32 + v / 32] >> (v % 32) & 1u) return false;
+            bits[(size_t)which * w32 + v / 32] |= 1u << (v % 32);
+        }
+        return true;
+    };
+    if (!add(R, nr, 0) || !add(P, np, 1) || !add(X, nx, 2)) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    if ((rc = g->d_sub.ensure(4ull * bits.size())) != MCE_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemcpyAsync(g->d_sub.p, bits.data(), 4ull * bits.size(), hipMemcpyHostToDevice, s));
+    rc = run_solve(g, 0, UINT64_MAX, res, s, nullptr, 0, nullptr, 0, nullptr, false, 0, g->d_sub.as<uint32_t>());
     if (rc != MCE_OK) res->status = rc;
     return rc;
 }

@@ -93,7 +93,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = (
     "mce_prepare", "mce_num_graphs", "mce_get_order", "mce_root_branches", "mce_count",
-    "mce_count_range", "mce_enumerate", "mce_submit", "mce_poll", "mce_cancel", "mce_release",
+    "mce_count_range", "mce_count_subproblem", "mce_enumerate", "mce_submit", "mce_poll", "mce_cancel", "mce_release",
     "mce_strerror", "mce_set_option", "mce_get_option", "mce_last_stats",
 )
 
@@ -124,6 +124,7 @@ def _lib():
         lib.mce_root_branches.argtypes = [vp, u32, p64]
         lib.mce_count.argtypes = [vp, pres, vp]
         lib.mce_count_range.argtypes = [vp, u64, u64, pres, vp]
+        lib.mce_count_subproblem.argtypes = [vp, p32, u32, p32, u32, p32, u32, pres, vp]
         lib.mce_enumerate.argtypes = [vp, vp, u64, vp, u64, p64, p64, pres, vp]
         lib.mce_submit.argtypes = [vp, u32, p64]
         lib.mce_poll.argtypes = [u64, pres, ctypes.c_int32]
@@ -271,6 +272,20 @@ class Graph:
         r, h = _new_result(self._n[0])
         _check(_lib().mce_count_range(self._h, first, last, ctypes.byref(r), _stream_ptr(stream)),
                "mce_count_range")
+        return _to_dict(r, h)
+
+    def count_subproblem(self, R, P, X, stream=None) -> dict:
+        """The search below node (R, P, X), vertices given as positions of the
+        ordering (see order())."""
+        def arr(x):
+            a = np.ascontiguousarray(list(x) or [0], dtype=np.uint32)
+            return a, len(x)
+        (ra, nr), (pa, npp), (xa, nx) = arr(R), arr(P), arr(X)
+        p32 = ctypes.POINTER(ctypes.c_uint32)
+        r, h = _new_result(self._n[0])
+        _check(_lib().mce_count_subproblem(self._h, ra.ctypes.data_as(p32), nr, pa.ctypes.data_as(p32), npp,
+                                           xa.ctypes.data_as(p32), nx, ctypes.byref(r), _stream_ptr(stream)),
+               "mce_count_subproblem")
         return _to_dict(r, h)
 
     def enumerate(self, verts=None, offsets=None, stream=None):

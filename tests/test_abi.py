@@ -122,6 +122,8 @@ def test_null_handles(lib, mce):
     res = mce.Result()
     assert lib.mce_count(None, ctypes.byref(res), None) == mce.E_INVAL
     assert lib.mce_count_range(None, 0, 1, ctypes.byref(res), None) == mce.E_INVAL
+    one = (ctypes.c_uint32 * 1)(0)
+    assert lib.mce_count_subproblem(None, None, 0, one, 1, None, 0, ctypes.byref(res), None) == mce.E_INVAL
     assert lib.mce_enumerate(None, None, 0, None, 0, None, None, ctypes.byref(res), None) == mce.E_INVAL
     n = ctypes.c_uint32()
     assert lib.mce_num_graphs(None, ctypes.byref(n)) == mce.E_INVAL

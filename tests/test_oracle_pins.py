@@ -391,3 +391,38 @@ def test_table1_step_calibration(orc):
         tb = np.mean([x["nodes"] for x in t]) / mu
         assert abs(gb / (r["greedybb_steps"] / r["mu"]) - 1.0) < 0.05, (r, gb)
         assert abs(tb / (r["tomitabb_steps"] / r["mu"]) - 1.0) < 0.08, (r, tb)
+
+
+def test_subproblem_partition(orc):
+    """The search split at the root's children (Alg. 4: child i of the root has
+    P = (V minus the earlier children) n N(l_i), X = earlier children n N(l_i))
+    adds up to the whole search; ids map positions back to input ids."""
+    n = 70
+    rows = synth.gnp(n, 0.5, 8)
+    order = orc.order(rows)
+    adj = synth.unpack_rows(rows)
+    pos = adj[np.ix_(order, order)]
+    rows_pos = synth.pack_rows(pos)
+    full = orc.greedy(rows)
+    root = orc.subproblem(rows_pos, [], list(range(n)), [], ids=order)
+    for k in ("count", "nodes", "children", "dead_ends", "hash_xor", "hash_sum", "omega", "hist"):
+        assert root[k] == full[k], k
+    # the root's pivot is position 0 (X is empty): L = {0} and its non-neighbours
+    L = [v for v in range(n) if v == 0 or not pos[0, v]]
+    assert len(L) == orc.root_branches(rows)
+    tot = dict(count=0, nodes=1, children=len(L), dead_ends=0, hash_xor=0, hash_sum=0)
+    earlier = []
+    for v in L:
+        P = [u for u in range(n) if u not in earlier and pos[v, u]]
+        X = [u for u in earlier if pos[v, u]]
+        if P or not X:
+            r = orc.subproblem(rows_pos, [v], P, X, ids=order)
+            for k in ("count", "nodes", "children", "dead_ends", "hash_sum"):
+                tot[k] += r[k]
+            tot["hash_xor"] ^= r["hash_xor"]
+        else:
+            tot["dead_ends"] += 1
+        earlier.append(v)
+    tot["hash_sum"] &= M64
+    for k in tot:
+        assert tot[k] == full[k], k
