@@ -1052,7 +1052,11 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                             kind = 3;
                             lds_st(&hdr->out, kOutReading);
                         } else if (st == kMailRefused) {
+                            // the cleared answer word must land before a new
+                            // question can be answered, or it could wipe that
+                            // answer out
                             st_dev(&sp.mail[me].state, kMailNone);
+                            vm_drain();
                             lds_st(&hdr->out, 0u);
                         }
                     }
@@ -1171,12 +1175,13 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 L[c] = in ? ld_dev(&rec[kRecHeader + 3 * CS + w]) : 0u;
             }
             if (src == 3) {
-                // the record is read: the mailbox may take the next answer
+                // the record is read: the mailbox may take the next answer,
+                // once the cleared answer word has landed (else it could
+                // wipe out that next answer)
                 vm_drain();
-                if (lane == 0) {
-                    st_dev(&sp.mail[me].state, kMailNone);
-                    lds_st(&hdr->out, 0u);
-                }
+                if (lane == 0) st_dev(&sp.mail[me].state, kMailNone);
+                vm_drain();
+                if (lane == 0) lds_st(&hdr->out, 0u);
             }
         }
         if (g != bcast0(ctx->g)) {

@@ -91,7 +91,7 @@ constexpr unsigned int kMailNone = 0u, kMailUnit = 1u, kMailRefused = 2u;
 
 // QueueCtl.error bits
 constexpr unsigned int kErrSpill = 1u; // spill pool exhausted: rerun with a larger pool
-constexpr unsigned int kErrDepth = 2u; // stack deeper than a spill chunk (a bug)
+constexpr unsigned int kErrDepth = 2u; // stack deeper than a spill chunk: rerun with chunks of full depth
 constexpr unsigned int kErrWatchdog = 4u; // the search ran past its deadline
 
 struct SearchParams {

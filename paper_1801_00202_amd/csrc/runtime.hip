@@ -318,7 +318,13 @@ size_t out_bytes(const mce_graph_s* h)
     return sizeof(DevResult) * h->num_graphs + sizeof(QueueCtl) + 8 * h->hist_total;
 }
 
-int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32_t blocks_cap = 0)
+// Stack levels a spill chunk holds at first: enough for every search of
+// these workloads; a deeper one stops with kErrDepth and reruns with chunks of
+// the full depth n - lds_depth.
+constexpr uint32_t kSpillLevelsFirst = 64;
+
+int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32_t blocks_cap = 0,
+             bool full_depth = false)
 {
     DeviceInfo di;
     int rc = device_info(&di);
@@ -361,6 +367,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     cap = std::max<uint64_t>(cap, (uint64_t)h->num_graphs + 1u);
     c.cap = next_pow2(cap);
     c.spill_levels = h->max_n > c.lds_depth ? h->max_n - c.lds_depth : 1u;
+    if (!full_depth) c.spill_levels = std::min(c.spill_levels, kSpillLevelsFirst);
     c.spill_chunks = std::max<uint32_t>(std::min<uint32_t>(waves, 64u), spill_chunks_floor);
     c.spill_chunks = std::min<uint32_t>(c.spill_chunks, waves);
     *cfg = c;
@@ -516,9 +523,10 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
     int rc = ensure_events(g);
     if (rc != MCE_OK) return rc;
     uint32_t floor = 0;
-    for (int attempt = 0; attempt < 3; attempt++) {
+    bool full_depth = false;
+    for (int attempt = 0; attempt < 4; attempt++) {
         LaunchCfg c;
-        if ((rc = make_cfg(g, &c, floor, blocks_cap)) != MCE_OK) return rc;
+        if ((rc = make_cfg(g, &c, floor, blocks_cap, full_depth)) != MCE_OK) return rc;
         if ((rc = ensure_workspace(g, c)) != MCE_OK) return rc;
         SearchParams sp = make_params(g, c);
         const bool enumerate = verts != nullptr || offs != nullptr;
@@ -580,8 +588,9 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
                          std::min(ctl.pool_next, ctl.pool_size), ctl.pool_size);
             return MCE_E_DEVICE;
         }
-        if (ctl.error & kErrSpill) {
-            floor = c.blocks * c.wpb; // one chunk for every wavefront
+        if (ctl.error & (kErrSpill | kErrDepth)) {
+            if (ctl.error & kErrSpill) floor = c.blocks * c.wpb; // one chunk for every wavefront
+            if (ctl.error & kErrDepth) full_depth = true;
             continue;
         }
         if (ctl.error) return MCE_E_DEVICE;
