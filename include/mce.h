@@ -72,7 +72,8 @@ extern "C" {
 #define MCE_OPT_GRAPH 8            /* mce_count replays a captured hipGraph of the solve:
                                       0 never, 1 for batch handles (default), 2 always */
 #define MCE_OPT_REFRESH_CHILDREN 9 /* children a busy workgroup processes between two looks
-                                      at its mailbox for workgroups asking for work (0 = auto) */
+                                      at its mailbox for workgroups asking for work (0 = auto:
+                                      the check interval, i.e. at every check) */
 
 typedef struct mce_graph_s *mce_graph_t; /* opaque; owns the device copy, order and rows */
 
@@ -222,6 +223,12 @@ typedef struct {
     uint64_t donations;    /* units handed to the queue by busy wavefronts */
     uint64_t units;        /* units processed */
     uint64_t spills;       /* stack levels written beyond the LDS window */
+    uint64_t checks;       /* times the search loop stopped to look at siblings and mailboxes */
+    uint64_t flushes;      /* times it stopped to hash a full clique buffer */
+    uint32_t attempts;     /* launches of the last call (a rerun follows an exhausted spill pool) */
+    uint32_t reserved;
+    double busy_frac;      /* share of the search kernel's wavefront time spent on units (the
+                              rest is looking for work and the end of the launch) */
 } mce_stats_t;
 
 int mce_last_stats(mce_stats_t *out);

@@ -16,6 +16,10 @@ FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
     # no packed fp32 instructions in any device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # branches that all lanes take alike stay plain scalar branches (the
+    # search loop has no lane-dependent branch; structurizing it would add
+    # exec-mask bookkeeping to every child)
+    "-mllvm", "-structurizecfg-skip-uniform-regions",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
 

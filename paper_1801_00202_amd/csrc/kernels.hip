@@ -605,19 +605,26 @@ __device__ __forceinline__ void wg_unlock(WgHdr* h, uint32_t lane)
 //   [kOffBuf, +kCliqueSlots)  clique buffer (16-bit halves of input-id bitsets)
 //   [kOffTrash, +64)   one word per lane for stores that must go nowhere
 //   [kOffCtx, +32)     WaveCtx: totals and bookkeeping used off the hot path
+//   [kOffSave, +128)   the search loop's lane registers while it is suspended:
+//                      idstk (64 words), then cent (64 words)
 //   [kWaveFixedWords, ...)  lds_depth stack frames, then the slot of the
 //                      current frame (written before a check), then slack
-// A frame holds P, X and L interleaved per lane: lane w's words of chunk c
-// sit at 3 (64 c + w) .. +2.
+// A frame holds P, X, L and the row of the frame's next candidate,
+// interleaved per lane: lane w's words of chunk c sit at 4 (64 c + w) .. +3.
 constexpr uint32_t kOffHist = 0, kOffBuf = kHistLds * 2, kOffTrash = kOffBuf + kCliqueSlots,
-                   kOffCtx = kOffTrash + 64;
-static_assert(kOffCtx + 32 == kWaveFixedWords, "layout");
+                   kOffCtx = kOffTrash + 64, kOffSave = kOffCtx + 32;
+static_assert(kOffSave + 128 == kWaveFixedWords, "layout");
 
 struct WaveCtx {
     unsigned long long count, nodes, children; // totals of graph g not yet folded into HBM
     unsigned long long units, donations, spills;
     uint32_t omega, g, spill_chunk, refreshes;
-    uint32_t pad[16];
+    unsigned long long hx, hs;                 // XOR and sum of the clique hashes of graph g
+    // the search loop's scalars while it is suspended (search_unit)
+    uint32_t d, budget, nent, used, rcount, refresh;
+    uint32_t checks, flushes; // suspensions of the search loop, by reason
+    unsigned long long busy;  // wall-clock ticks spent on units
+    uint32_t pad[2];
 };
 static_assert(sizeof(WaveCtx) == 32 * 4, "ctx size");
 
@@ -629,23 +636,17 @@ template <int WPL> struct LaneBits {
     uint32_t w[WPL];
 };
 
-// Per-lane XOR and sum of the hashes of flushed cliques, kept in registers.
-struct LaneAcc {
-    uint64_t x, s;
-};
-
 // Hash, histogram and (enumerate) write-out of the nent buffered cliques, one
 // clique per lane: lane i's clique is the list of halves at buffer words
-// [start, start + cnt), with cent (this lane's value) = start << 16 | cnt.
-// Off the hot path.
-__device__ __attribute__((noinline)) LaneAcc cold_flush(const SearchParams* __restrict__ spp, uint32_t* wl,
-                                                        uint32_t cent, uint32_t nent_v, uint32_t hist_off_lo,
-                                                        uint32_t hist_off_hi, LaneAcc acc)
+// [start, start + cnt), with cent (lane i's saved word) = start << 16 | cnt.
+// Empties the buffer.  Off the hot path.
+__device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restrict__ spp, uint32_t* wl,
+                                                     uint64_t hoff)
 {
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
-    const uint32_t nent = bcast0(nent_v);
-    const uint64_t hoff = ((uint64_t)bcast0(hist_off_hi) << 32) | bcast0(hist_off_lo);
+    const uint32_t nent = bcast0(wave_ctx(wl)->nent);
+    const uint32_t cent = wl[kOffSave + 64 + lane];
     unsigned long long* ghist = sp.hist + hoff;
     unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl + kOffHist);
     const uint32_t* buf = wl + kOffBuf;
@@ -656,8 +657,9 @@ __device__ __attribute__((noinline)) LaneAcc cold_flush(const SearchParams* __re
     // clique size, then the hash chain over the ids in increasing order
     uint32_t k = 0;
     for (uint32_t i = 0; i < cnt; i++) k += (uint32_t)__builtin_popcount(buf[st + i] & 0xffffu);
+    uint64_t h = 0;
     if (mine) {
-        uint64_t h = mix64((uint64_t)k);
+        h = mix64((uint64_t)k);
         for (uint32_t i = 0; i < cnt; i++) {
             const uint32_t e = buf[st + i];
             const uint32_t base = (e >> 16) << 4;
@@ -667,8 +669,12 @@ __device__ __attribute__((noinline)) LaneAcc cold_flush(const SearchParams* __re
                 bits &= bits - 1u;
             }
         }
-        acc.x ^= h;
-        acc.s += h;
+    }
+    // XOR and sum over the lanes (lanes without a clique hold 0)
+    uint64_t hx = h, hs = h;
+    for (int off = 32; off > 0; off >>= 1) {
+        hx ^= __shfl_xor(hx, off);
+        hs += __shfl_xor(hs, off);
     }
     uint64_t rem = ballot(mine);
     uint32_t kmax = 0;
@@ -677,6 +683,8 @@ __device__ __attribute__((noinline)) LaneAcc cold_flush(const SearchParams* __re
         const uint32_t k0 = rdlane(k, l0);
         const uint64_t m = ballot(mine && k == k0);
         const uint32_t c = (uint32_t)__builtin_popcountll(m);
+        // counted in LDS (all waves share few sizes: HBM atomics would queue
+        // on the same words); sizes past the LDS histogram go to HBM
         if (lane == 0) {
             if (k0 < kHistLds) hist_l[k0] += c;
             else atomicAdd(&ghist[k0], (unsigned long long)c);
@@ -687,6 +695,10 @@ __device__ __attribute__((noinline)) LaneAcc cold_flush(const SearchParams* __re
     if (lane == 0) {
         ctx->count += nent;
         ctx->omega = umax32(ctx->omega, kmax);
+        ctx->hx ^= hx;
+        ctx->hs += hs;
+        ctx->nent = 0;
+        ctx->used = 0;
     }
     if (sp.enumerate) {
         // ids of clique i at verts[vb + (sizes of cliques before i)], and its
@@ -716,13 +728,11 @@ __device__ __attribute__((noinline)) LaneAcc cold_flush(const SearchParams* __re
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    return acc;
 }
 
-// Fold the wavefront's totals of graph ctx->g (and its hash accumulators)
-// into HBM and clear them.
-__device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restrict__ spp, uint32_t* wl,
-                                                    LaneAcc acc)
+// Fold the wavefront's totals of graph ctx->g (counts, hash totals, omega,
+// histogram) into HBM and clear them.
+__device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restrict__ spp, uint32_t* wl)
 {
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
@@ -730,11 +740,7 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
     const uint32_t g = bcast0(ctx->g);
     if (g == 0xffffffffu) return;
     unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl + kOffHist);
-    uint64_t x = acc.x, s = acc.s;
-    for (int off = 32; off > 0; off >>= 1) {
-        x ^= __shfl_xor(x, off);
-        s += __shfl_xor(s, off);
-    }
+    const uint64_t x = ctx->hx, s = ctx->hs;
     const uint64_t hoff = sp.graphs[g].hist_off;
     if (lane == 0) {
         DevResult* r = sp.results + g;
@@ -745,6 +751,7 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
         if (s) atomicAdd(&r->hash_sum, (unsigned long long)s);
         if (ctx->omega) atomicMax(&r->omega, ctx->omega);
         ctx->count = ctx->nodes = ctx->children = 0;
+        ctx->hx = ctx->hs = 0;
         ctx->omega = 0;
     }
     for (uint32_t i = lane; i < kHistLds; i += 64) {
@@ -756,21 +763,20 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
     }
 }
 
-// The look at siblings and at the mailbox every check_interval children.  The
-// current frame is in its LDS slot; frames 0..d-1 are on the stack.  May hand
-// the later half of the candidates of the shallowest big-enough frame to the
-// LDS LIFO or to the workgroup that asked (the current frame's L in its slot
-// is updated then).  Returns 1 if the search must stop.
+// The look at siblings and at the mailbox, when the periodic check of the
+// search loop finds something to do.  The loop is suspended: the current
+// frame (P, X, L, R) is in its LDS slot, frames 0..d-1 are on the stack, d and
+// the ids of the pushed children are in the save area.  May hand the later
+// half of the candidates of the shallowest big-enough frame to the LDS LIFO
+// or to the workgroup that asked (the current frame's L in its slot is updated
+// then).  Returns 1 if the search must stop.
 template <int WPL>
 __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __restrict__ spp, uint32_t* smem,
-                                                         uint32_t* wl, uint32_t d_v, uint32_t W_v, uint32_t g_v,
-                                                         LaneBits<WPL> Rbb, uint32_t idstk, uint64_t t_start,
-                                                         uint32_t refresh_v)
+                                                         uint32_t* wl, uint32_t W_v, uint32_t g_v, uint64_t t_start)
 {
-    const uint32_t (&Rb)[WPL] = Rbb.w;
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
-    const uint32_t d = bcast0(d_v), W = bcast0(W_v), g = bcast0(g_v);
+    const uint32_t W = bcast0(W_v), g = bcast0(g_v);
     const uint32_t NW = blockDim.x >> 6;
     WgHdr* hdr = reinterpret_cast<WgHdr*>(smem);
     uint32_t* lq = smem + kWgHdrWords;
@@ -779,11 +785,17 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
     uint32_t* stk = wl + kWaveFixedWords;
     uint32_t* cur = stk + (size_t)sp.lds_depth * SW;
     const uint32_t chunk = bcast0(ctx->spill_chunk);
+    const uint32_t d = bcast0(ctx->d);
+    const uint32_t refresh_v = bcast0(ctx->refresh);
+    const uint32_t idstk = wl[kOffSave + lane];
+    uint32_t Rb[WPL];
+#pragma unroll
+    for (int c = 0; c < WPL; c++) Rb[c] = cur[4u * ((uint32_t)c * 64u + lane) + 3u];
     // word t (0: P, 1: X, 2: L) of chunk c of frame s, for this lane
     auto fword = [&](uint32_t s, int c, uint32_t t) -> uint32_t* {
         const uint32_t li = (uint32_t)c * 64u + lane;
-        if (s == d) return cur + 3u * li + t;
-        if (s < sp.lds_depth) return stk + (size_t)s * SW + 3u * li + t;
+        if (s == d) return cur + 4u * li + t;
+        if (s < sp.lds_depth) return stk + (size_t)s * SW + 4u * li + t;
         return sp.spill + ((size_t)chunk * sp.spill_levels + (s - sp.lds_depth)) * SPW + 4u * li + t;
     };
     // input id of the child pushed from frame j (j < d)
@@ -812,10 +824,17 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
         }
         asker = bcast0(a);
     }
-    if (!to_local && asker == 0u && lqn == 0u) to_local = true;
+    // Units to hand out now: one to the asker; to the LIFO one per waiting
+    // sibling (or one to keep in stock).  Each comes from the shallowest frame
+    // that can still be split, so a frame may give several in turn.
+    uint32_t n_local = 0;
+    if (to_local) n_local = umin32(NW - busy - lqn, kLocalSlots - lqn);
+    else if (asker == 0u && lqn == 0u) n_local = 1;
+    const uint32_t rounds = n_local + (asker != 0u ? 1u : 0u);
     bool gave = false;
-    if (to_local || asker != 0u) {
-        for (uint32_t s = 0; s <= d; s++) {
+    uint32_t given = 0;
+    if (rounds != 0u) {
+        for (uint32_t s = 0; s <= d && given < rounds;) {
             uint32_t Ls[WPL], Ps[WPL], Xs[WPL], cnt[WPL], incl[WPL];
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
@@ -823,7 +842,10 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                 Ls[c] = (w < W) ? *fword(s, c, 2) : 0u;
             }
             const uint32_t tot = popc_scan<WPL>(Ls, cnt, incl);
-            if (tot < 2) continue;
+            if (tot < 2) {
+                s++;
+                continue;
+            }
             uint32_t pc = 0;
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
@@ -848,7 +870,7 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
             // R of frame s: drop the children pushed from frames s..d-1
             for (uint32_t j = s; j < d; j++) clear_bit<WPL>(Rs, child_id(j), lane);
             bool ok;
-            if (asker != 0u) {
+            if (asker != 0u && !gave) {
                 // the unit is in transit until the asker takes it: count it
                 // before it becomes visible
                 store_record<WPL>(sp.mail_rec + (size_t)(asker - 1u) * RW, CS, lane, g, W, Rs, Pd, Xd, L2);
@@ -884,9 +906,11 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                     if (w < W) *fword(s, c, 2) = L1[c];
                 }
                 if (lane == 0) ctx->donations += 1;
-                gave = true;
+                gave = gave || asker != 0u;
+                given++;
+            } else {
+                break; // the LIFO is full
             }
-            break;
         }
     }
     if (asker != 0u && !gave && lane == 0) st_dev(&sp.mail[asker - 1u].state, kMailRefused);
@@ -923,6 +947,386 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
         }
     }
     return 0;
+}
+
+// Spill chunk of this wavefront, for stack levels below its LDS window: taken
+// from the pool on first use.  Returns 0xffffffff (and flags the launch for a
+// rerun with a larger pool) when the pool is exhausted.
+__device__ __attribute__((noinline)) uint32_t cold_spill_chunk(const SearchParams* __restrict__ spp, uint32_t* wl)
+{
+    const SearchParams& sp = *spp;
+    const uint32_t lane = lane_id();
+    uint32_t ch = 0;
+    if (lane == 0) ch = (uint32_t)atomicAdd(&sp.ctl->spill_next, 1ull);
+    ch = bcast0(ch);
+    if (ch >= sp.spill_chunks) {
+        if (lane == 0) atomicOr(&sp.ctl->error, kErrSpill);
+        return 0xffffffffu;
+    }
+    if (lane == 0) wave_ctx(wl)->spill_chunk = ch;
+    return ch;
+}
+
+// Flag the launch with error bits (QueueCtl.error).
+__device__ __attribute__((noinline)) void cold_error(const SearchParams* __restrict__ spp, uint32_t bits_v)
+{
+    const uint32_t bits = bcast0(bits_v);
+    if (lane_id() == 0) atomicOr(&spp->ctl->error, bits);
+}
+
+// Address-space views used by search_unit: constant (read-only during a
+// launch: scalar loads) and global.
+typedef const __attribute__((address_space(4))) SearchParams CParams;
+typedef const __attribute__((address_space(4))) GraphDesc CGraphDesc;
+typedef __attribute__((address_space(1))) uint32_t GU32;
+
+// Why search_unit returned.
+constexpr uint32_t kUnitDone = 0, kUnitAbort = 1, kUnitCheck = 2, kUnitFlush = 3, kUnitChunk = 4, kUnitDepth = 5;
+
+// The search of one unit (R, P, X, L) of graph g by one wavefront: Alg. 4
+// from that node, branching only on the candidates in L.  The loop calls no
+// function and has no lane-dependent branch, so that its registers stay few:
+// whenever something must be done off the hot path (look at the siblings and
+// the mailbox, hash a full clique buffer, take a spill chunk) it stores its
+// state in LDS and returns why (kUnit*); the caller does it and calls again
+// with resume = 1.  Counters since the last return are added to the
+// wavefront's totals before every return.  wl_off: word offset of the
+// wavefront's LDS block.
+template <int WPL>
+__device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __restrict__ spp_v, uint32_t wl_off,
+                                                          LaneBits<WPL> Rbb, LaneBits<WPL> Pb, LaneBits<WPL> Xb,
+                                                          LaneBits<WPL> Lb, uint32_t g_v, uint32_t resume_v)
+{
+    extern __shared__ uint32_t smem[];
+    // The parameter block and the graph descriptors do not change during a
+    // launch: read through a wave-uniform pointer in the constant address
+    // space they are scalar loads into scalar registers.  The spill pool is addressed as global memory
+    // (a generic access would be a FLAT one, after which every wait for a
+    // row load must wait for all loads).
+    const uint64_t spa = reinterpret_cast<uint64_t>(spp_v);
+    const CParams& sp = *(const CParams*)(((uint64_t)bcast0((uint32_t)(spa >> 32)) << 32) | bcast0((uint32_t)spa));
+    const uint32_t lane = lane_id();
+    const uint32_t NW = blockDim.x >> 6;
+    WgHdr* hdr = reinterpret_cast<WgHdr*>(smem);
+    uint32_t* wl = smem + bcast0(wl_off);
+    WaveCtx* ctx = wave_ctx(wl);
+    const uint32_t g = bcast0(g_v);
+    const bool resume = bcast0(resume_v) != 0u;
+    const CGraphDesc& gd = ((const CGraphDesc*)(sp.graphs))[g];
+    const uint64_t adj_off = gd.adj_off;
+    const uint32_t W = gd.w32;
+    const uint32_t rs4 = 4u * gd.rstride;
+    // renumbered rows through a buffer resource: a row is addressed by a
+    // scalar offset (v * row stride) plus this lane's word offset
+    const uint64_t abase = reinterpret_cast<uint64_t>(sp.adj) + 4ull * adj_off;
+    const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void*>(abase), (short)0, (int)(gd.n * rs4), 0x00020000);
+    const uint32_t* ord = sp.order + gd.ord_off;
+    uint32_t lane_lo[WPL], voff[WPL];
+    bool live[WPL];
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t li = (uint32_t)c * 64u + lane;
+        lane_lo[c] = li << 5;
+        voff[c] = li << 2;
+        live[c] = li < W;
+    }
+    // input id of the vertex whose row is in r: the word after the row
+    auto row_id = [&](const uint32_t (&r)[WPL], uint32_t v) -> uint32_t {
+        if (WPL == 1) return rdlane(r[0], W);
+        if (W < 64u) return rdlane(r[0], W);
+        if (W < 128u) return rdlane(r[WPL - 1], W - 64u);
+        return bcast0(ord[v]);
+    };
+    (void)ord;
+    const uint32_t lds_depth = sp.lds_depth;
+    const uint32_t ci = sp.check_interval;
+    const uint32_t ci_fast = umax32(ci >> 2, 1u);
+    const uint32_t SW = sp.slot_words, SPW = sp.spill_words;
+    const uint32_t spill_levels = sp.spill_levels;
+    GU32* const spill = (GU32*)(sp.spill);
+    uint32_t* stk = wl + kWaveFixedWords;
+    uint32_t* cur = stk + (size_t)lds_depth * SW;
+    uint32_t* buf = wl + kOffBuf;
+    uint32_t* trash = wl + kOffTrash;
+    uint32_t* save = wl + kOffSave;
+    // A workgroup looks at its mailbox about once per refresh_children of its
+    // children: each of its busy wavefronts every busy * (refresh_children /
+    // ci) of its own checks (busy as seen at its last look), at staggered
+    // phases, so that a workgroup with one busy wavefront still answers as
+    // often as a full one.
+    const uint32_t rstep = umax32(sp.refresh_children / ci, 1u);
+    uint32_t Rb[WPL], P[WPL], X[WPL], L[WPL];
+    uint32_t d, budget, nent, used, rcount, idstk, cent;
+    if (!resume) {
+#pragma unroll
+        for (int c = 0; c < WPL; c++) {
+            Rb[c] = Rbb.w[c];
+            P[c] = Pb.w[c];
+            X[c] = Xb.w[c];
+            L[c] = Lb.w[c];
+        }
+        d = 0;
+        budget = ci;
+        nent = bcast0(ctx->nent);
+        used = bcast0(ctx->used);
+        rcount = (bcast0(threadIdx.x >> 6) * rstep) % (umax32(bcast0(lds_ld(&hdr->busy)), 1u) * rstep) + 1u;
+        idstk = 0;
+        cent = save[64 + lane];
+    } else {
+#pragma unroll
+        for (int c = 0; c < WPL; c++) {
+            const uint32_t li = (uint32_t)c * 64u + lane;
+            const uint4 q = *reinterpret_cast<const uint4*>(cur + 4u * li);
+            P[c] = live[c] ? q.x : 0u;
+            X[c] = live[c] ? q.y : 0u;
+            L[c] = live[c] ? q.z : 0u;
+            Rb[c] = live[c] ? q.w : 0u;
+        }
+        d = bcast0(ctx->d);
+        budget = bcast0(ctx->budget);
+        nent = bcast0(ctx->nent);
+        used = bcast0(ctx->used);
+        rcount = bcast0(ctx->rcount);
+        idstk = save[lane];
+        cent = save[64 + lane];
+    }
+    uint32_t chunk = bcast0(ctx->spill_chunk);
+    uint32_t kids = 0;   // children examined since the last return
+    uint32_t nodes = 0;  // nodes created since then
+    uint32_t spills = 0; // frames written to the spill pool since then
+    uint32_t why = kUnitDone;
+    // Row v into r (one word per lane); the load is only issued here, and
+    // the first use of r waits for it.
+    auto load_row = [&](uint32_t v, uint32_t (&r)[WPL]) {
+        const uint32_t so = v * rs4;
+#pragma unroll
+        for (int c = 0; c < WPL; c++)
+            r[c] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rows, (int)voff[c], (int)so, 0);
+    };
+    // cv: the first candidate left in L (-1: none); crow: its row.  The row
+    // of the candidate after it is requested before the child cv is
+    // examined, and an LDS frame keeps the row of its next candidate, so that
+    // returning to a parent costs no row load.
+    uint32_t crow[WPL];
+    int cv = first_pos<WPL>(L, lane_lo);
+    load_row(cv >= 0 ? (uint32_t)cv : 0u, crow);
+
+    for (;;) {
+        if (cv < 0) {
+            // node finished: return to the parent frame
+            if (d == 0) break;
+            d--;
+            uint32_t idp;
+            if (d < lds_depth) {
+                const uint32_t* f = stk + (size_t)d * SW;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    const uint32_t li = (uint32_t)c * 64u + lane;
+                    const uint4 q = *reinterpret_cast<const uint4*>(f + 4u * li);
+                    P[c] = live[c] ? q.x : 0u;
+                    X[c] = live[c] ? q.y : 0u;
+                    L[c] = live[c] ? q.z : 0u;
+                    crow[c] = q.w;
+                }
+                idp = rdlane(idstk, d);
+                cv = first_pos<WPL>(L, lane_lo);
+            } else {
+                const GU32* f = spill + ((size_t)chunk * spill_levels + (d - lds_depth)) * SPW;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    const uint32_t li = (uint32_t)c * 64u + lane;
+                    P[c] = f[4 * li];
+                    X[c] = f[4 * li + 1];
+                    L[c] = f[4 * li + 2];
+                }
+                idp = bcast0(f[3]);
+                cv = first_pos<WPL>(L, lane_lo);
+                load_row(cv >= 0 ? (uint32_t)cv : 0u, crow);
+            }
+            uint32_t m[WPL];
+            bit_mask<WPL>(idp, lane_lo, m);
+#pragma unroll
+            for (int c = 0; c < WPL; c++) Rb[c] &= ~m[c];
+            continue;
+        }
+        // a push below the LDS window needs a spill chunk, and room in it
+        if (d >= lds_depth) {
+            if (chunk == 0xffffffffu) {
+                why = kUnitChunk;
+                break;
+            }
+            if (d - lds_depth >= spill_levels) {
+                why = kUnitDepth;
+                break;
+            }
+        }
+        const uint32_t v = (uint32_t)cv;
+        uint32_t m[WPL];
+        bit_mask<WPL>(v, lane_lo, m);
+#pragma unroll
+        for (int c = 0; c < WPL; c++) L[c] &= ~m[c];
+        // the next candidate's row is on its way while v is examined (with
+        // no candidate left, row v again: a load on every path lets the wait
+        // for crow below leave this one in flight)
+        const int nv = first_pos<WPL>(L, lane_lo);
+        uint32_t nrow[WPL];
+        load_row(nv >= 0 ? (uint32_t)nv : v, nrow);
+        // step 11: P' = P n N(v), X' = X n N(v)
+        uint32_t P2[WPL], X2[WPL];
+#pragma unroll
+        for (int c = 0; c < WPL; c++) {
+            P2[c] = P[c] & crow[c];
+            X2[c] = X[c] & crow[c];
+            // steps 12-13 for the current node
+            P[c] &= ~m[c];
+            X[c] |= m[c];
+        }
+        kids++;
+        if (any_set<WPL>(P2)) {
+            // the child is a node: push the current frame, descend
+            const uint32_t idv = row_id(crow, v);
+            nodes++;
+            const uint32_t dp = d;
+            if (d < lds_depth) {
+                uint32_t* f = stk + (size_t)d * SW;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    const uint32_t li = (uint32_t)c * 64u + lane;
+                    f[4 * li] = P[c];
+                    f[4 * li + 1] = X[c];
+                    f[4 * li + 2] = L[c];
+                }
+                idstk = (lane == d) ? idv : idstk;
+            } else {
+                GU32* fs = spill + ((size_t)chunk * spill_levels + (d - lds_depth)) * SPW;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    const uint32_t li = (uint32_t)c * 64u + lane;
+                    fs[4 * li] = P[c];
+                    fs[4 * li + 1] = X[c];
+                    fs[4 * li + 2] = L[c];
+                    fs[4 * li + 3] = idv;
+                }
+                spills++;
+            }
+            d++;
+            uint32_t mi[WPL];
+            bit_mask<WPL>(idv, lane_lo, mi);
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                Rb[c] |= mi[c];
+                P[c] = P2[c];
+                X[c] = X2[c];
+            }
+            // step 9: pivot = first of X if X is non-empty, else first of P.
+            // The row of the first of P is requested with the pivot's: it is
+            // the first candidate whenever it is not adjacent to the pivot
+            // (always when the pivot is that vertex).
+            const int px = first_pos<WPL>(X, lane_lo);
+            const int pp = first_pos<WPL>(P, lane_lo);
+            const uint32_t piv = px >= 0 ? (uint32_t)px : (uint32_t)pp;
+            uint32_t prow[WPL], frow[WPL];
+            load_row(piv, prow);
+            load_row((uint32_t)pp, frow);
+            // step 10: L = P \ N(p)
+#pragma unroll
+            for (int c = 0; c < WPL; c++) L[c] = P[c] & ~prow[c];
+            // the parent's next row, requested before the pivot's, is in:
+            // keep it with the parent frame
+            if (dp < lds_depth && nv >= 0) {
+                uint32_t* f = stk + (size_t)dp * SW;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) f[4 * ((uint32_t)c * 64u + lane) + 3] = nrow[c];
+            }
+            cv = first_pos<WPL>(L, lane_lo);
+            if (cv == pp) {
+#pragma unroll
+                for (int c = 0; c < WPL; c++) crow[c] = frow[c];
+            } else if (cv >= 0) {
+                load_row((uint32_t)cv, crow);
+            }
+        } else {
+            if (!any_set<WPL>(X2)) {
+                // P' and X' empty: R u {v} is maximal.  R is the bitset Rb over
+                // input ids; its non-empty 16-bit halves, in lane order, are the
+                // clique's sorted ids.  The buffer always has room for one
+                // more clique (it is emptied before it could run out).
+                const uint32_t idv = row_id(crow, v);
+                uint32_t mi[WPL];
+                bit_mask<WPL>(idv, lane_lo, mi);
+                const uint32_t start = used;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    const uint32_t cw = Rb[c] | mi[c];
+                    const uint32_t lo = cw & 0xffffu, hi = cw >> 16;
+                    const uint64_t blo = ballot(lo != 0u), bhi = ballot(hi != 0u);
+                    const uint32_t below =
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(blo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)blo, 0u)) +
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(bhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bhi, 0u));
+                    const uint32_t plo = used + below;
+                    const uint32_t phi = plo + (lo != 0u ? 1u : 0u);
+                    const uint32_t hw = (((uint32_t)c * 64u + lane) << 1);
+                    *(lo != 0u ? buf + plo : trash + lane) = (hw << 16) | lo;
+                    *(hi != 0u ? buf + phi : trash + lane) = ((hw + 1u) << 16) | hi;
+                    used += (uint32_t)__builtin_popcountll(blo) + (uint32_t)__builtin_popcountll(bhi);
+                }
+                cent = (lane == nent) ? ((start << 16) | (used - start)) : cent;
+                nent++;
+            }
+            cv = nv;
+#pragma unroll
+            for (int c = 0; c < WPL; c++) crow[c] = nrow[c];
+        }
+
+        // a full clique buffer is emptied at once
+        if (nent == 64u || used + 2u * 64u * WPL > kCliqueSlots) {
+            why = kUnitFlush;
+            break;
+        }
+        if (--budget == 0u) {
+            // Look at the siblings and the workgroup's flags (LDS only);
+            // suspend for the out-of-line look only when there is something
+            // to do.  While siblings wait, look four times as often.
+            const uint32_t busy = bcast0(lds_ld(&hdr->busy));
+            const uint32_t lqn = bcast0(lds_ld(&hdr->lq_n));
+            const uint32_t dn = bcast0(lds_ld(&hdr->done));
+            const uint32_t asked = bcast0(lds_ld(&hdr->req));
+            const bool waiting = lqn < kLocalSlots && NW - busy > lqn;
+            budget = waiting ? ci_fast : ci;
+            const uint32_t refresh = --rcount == 0u;
+            if (refresh) rcount = umax32(busy, 1u) * rstep;
+            if (dn) {
+                why = kUnitAbort;
+                break;
+            }
+            if (refresh || asked || lqn == 0u || waiting) {
+                // every lane stores the same value: no lane-dependent branch
+                ctx->refresh = refresh;
+                why = kUnitCheck;
+                break;
+            }
+        }
+    }
+    // Suspend (or finish): the loop's state to LDS, the counters to the totals.
+    if (why != kUnitDone && why != kUnitAbort) {
+#pragma unroll
+        for (int c = 0; c < WPL; c++) {
+            const uint32_t li = (uint32_t)c * 64u + lane;
+            *reinterpret_cast<uint4*>(cur + 4u * li) = make_uint4(P[c], X[c], L[c], Rb[c]);
+        }
+        save[lane] = idstk;
+        ctx->d = d;
+        ctx->budget = budget;
+        ctx->rcount = rcount;
+    }
+    save[64 + lane] = cent;
+    ctx->nent = nent;
+    ctx->used = used;
+    ctx->nodes = ctx->nodes + nodes;
+    ctx->children = ctx->children + kids;
+    ctx->spills = ctx->spills + spills;
+    return why;
 }
 
 template <int WPL>
@@ -974,9 +1378,6 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
 
     const uint32_t me = blockIdx.x;
     uint32_t backoff = 1, idle_iters = 0, polls = 0;
-    LaneAcc acc;
-    acc.x = 0;
-    acc.s = 0;
     for (;;) {
         // ================= obtain a unit =================
         // src 1: the LDS LIFO (slot lsl), 2: the pool of root units (index
@@ -994,6 +1395,23 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                         give_up();
                         stop = true;
                         break;
+                    }
+                    // While siblings are busy, a waiting wavefront takes
+                    // questions from other workgroups out of the mailbox, so
+                    // that a busy sibling answers at its next check (LDS
+                    // only) instead of reading the mailbox itself.
+                    if ((idle_iters & 3u) == 0u && lane == 0 && lds_ld(&hdr->busy) != 0u &&
+                        lds_ld(&hdr->req) == 0u) {
+                        unsigned int* mreq = &sp.mail[me].req;
+                        if (ld_dev(mreq) != 0u) {
+                            const uint32_t a =
+                                __hip_atomic_exchange(mreq, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            uint32_t zero = 0u;
+                            if (a != 0u && !__hip_atomic_compare_exchange_strong(&hdr->req, &zero, a,
+                                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+                                st_dev(&sp.mail[a - 1u].state, kMailRefused);
+                        }
                     }
                     __builtin_amdgcn_s_sleep(16);
                     continue;
@@ -1144,7 +1562,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         set_state(kWaveBusy);
 
         // ================= load the unit =================
-        const uint32_t CS = sp.w32cap, SW = sp.slot_words, SPW = sp.spill_words;
+        const uint32_t CS = sp.w32cap;
         uint32_t Rb[WPL], P[WPL], X[WPL], L[WPL];
         uint32_t g;
         if (src == 1) {
@@ -1185,262 +1603,45 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
             }
         }
         if (g != bcast0(ctx->g)) {
-            cold_fold(spp, wl, acc);
-            acc.x = 0;
-            acc.s = 0;
+            cold_fold(spp, wl);
             if (lane == 0) ctx->g = g;
         }
         if (lane == 0) ctx->units += 1;
 
         // ================= the search of the unit (Alg. 4) =================
-        const GraphDesc& gd = sp.graphs[g];
-        const uint32_t W = bcast0(gd.w32);
-        const uint32_t rs4 = 4u * bcast0(gd.rstride);
-        // renumbered rows through a buffer resource: a row is addressed by a
-        // scalar offset (v * row stride) plus this lane's word offset; reads
-        // past the rows return 0
-        const uint64_t abase = reinterpret_cast<uint64_t>(sp.adj + gd.adj_off);
-        const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
-            reinterpret_cast<void*>(((uint64_t)bcast0((uint32_t)(abase >> 32)) << 32) | bcast0((uint32_t)abase)),
-            (short)0, (int)(bcast0(gd.n) * rs4), 0x00020000);
-        const uint32_t* ord = sp.order + gd.ord_off;
-        const uint32_t hoff_lo = (uint32_t)gd.hist_off, hoff_hi = (uint32_t)(gd.hist_off >> 32);
-        uint32_t lane_lo[WPL], voff[WPL];
-        bool live[WPL];
+        const uint64_t t_unit = wall_clock64();
+        LaneBits<WPL> ub[4];
 #pragma unroll
         for (int c = 0; c < WPL; c++) {
-            const uint32_t li = (uint32_t)c * 64u + lane;
-            lane_lo[c] = li << 5;
-            voff[c] = li << 2;
-            live[c] = li < W;
+            ub[0].w[c] = Rb[c];
+            ub[1].w[c] = P[c];
+            ub[2].w[c] = X[c];
+            ub[3].w[c] = L[c];
         }
-        // input id of the vertex whose row is in r: the word after the row
-        auto row_id = [&](const uint32_t (&r)[WPL], uint32_t v) -> uint32_t {
-            if (WPL == 1) return rdlane(r[0], W);
-            if (W < 64u) return rdlane(r[0], W);
-            if (W < 128u) return rdlane(r[WPL - 1], W - 64u);
-            return bcast0(ord[v]);
-        };
-        (void)ord;
-        const uint32_t lds_depth = sp.lds_depth;
-        const uint32_t ci = sp.check_interval;
-        const uint32_t refresh_children = sp.refresh_children;
-        uint32_t* stk = wl + kWaveFixedWords;
-        uint32_t* cur = stk + (size_t)lds_depth * SW;
-        uint32_t* buf = wl + kOffBuf;
-        uint32_t* trash = wl + kOffTrash;
-        uint32_t d = 0;          // frames of this unit on the stack
-        uint32_t budget = ci;    // children until the next check
-        uint32_t kids = 0;       // children examined since the last check
-        uint32_t nodes = 0;      // nodes created since the last check
-        uint32_t nent = 0, used = 0, cent = 0; // clique buffer: cliques, words, lane i: start << 16 | words
-        uint32_t idstk = 0;      // lane j: input id of the child pushed from frame j < lds_depth
-        uint32_t chunk = bcast0(ctx->spill_chunk);
+        const uint32_t wl_off = (uint32_t)(wl - smem);
+        const uint32_t W = bcast0(sp.graphs[g].w32);
         bool abort = false;
-
-        for (;;) {
-            const int vi = first_pos<WPL>(L, lane_lo);
-            if (vi < 0) {
-                // node finished: return to the parent frame
-                if (d == 0) break;
-                d--;
-                uint32_t idp;
-                if (d < lds_depth) {
-                    const uint32_t* f = stk + (size_t)d * SW;
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) {
-                        const uint32_t li = (uint32_t)c * 64u + lane;
-                        const uint32_t p0 = f[3 * li], x0 = f[3 * li + 1], l0 = f[3 * li + 2];
-                        P[c] = live[c] ? p0 : 0u;
-                        X[c] = live[c] ? x0 : 0u;
-                        L[c] = live[c] ? l0 : 0u;
-                    }
-                    idp = rdlane(idstk, d);
-                } else {
-                    const uint32_t* f = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SPW;
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) {
-                        const uint32_t li = (uint32_t)c * 64u + lane;
-                        P[c] = f[4 * li];
-                        X[c] = f[4 * li + 1];
-                        L[c] = f[4 * li + 2];
-                    }
-                    idp = bcast0(f[3]);
-                }
-                uint32_t m[WPL];
-                bit_mask<WPL>(idp, lane_lo, m);
-#pragma unroll
-                for (int c = 0; c < WPL; c++) Rb[c] &= ~m[c];
-                continue;
+        for (uint32_t resume = 0;; resume = 1) {
+            const uint32_t why = bcast0(search_unit<WPL>(spp, wl_off, ub[0], ub[1], ub[2], ub[3], g, resume));
+            if (why == kUnitDone) break;
+            if (why == kUnitCheck) {
+                if (lane == 0) ctx->checks += 1;
+                abort = bcast0(cold_check<WPL>(spp, smem, wl, W, g, t_start)) != 0u;
+            } else if (why == kUnitFlush) {
+                if (lane == 0) ctx->flushes += 1;
+                cold_flush(spp, wl, sp.graphs[g].hist_off);
+            } else if (why == kUnitChunk) {
+                abort = bcast0(cold_spill_chunk(spp, wl)) == 0xffffffffu;
+            } else {
+                if (why == kUnitDepth) cold_error(spp, kErrDepth);
+                abort = true;
             }
-            const uint32_t v = (uint32_t)vi;
-            // step 11: P' = P n N(v), X' = X n N(v)
-            const uint32_t soff = v * rs4;
-            uint32_t row[WPL];
-#pragma unroll
-            for (int c = 0; c < WPL; c++)
-                row[c] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rows, (int)voff[c], (int)soff, 0);
-            uint32_t m[WPL], P2[WPL], X2[WPL];
-            bit_mask<WPL>(v, lane_lo, m);
-#pragma unroll
-            for (int c = 0; c < WPL; c++) {
-                L[c] &= ~m[c];
-                P2[c] = P[c] & row[c];
-                X2[c] = X[c] & row[c];
-                // steps 12-13 for the current node
-                P[c] &= ~m[c];
-                X[c] |= m[c];
-            }
-            kids++;
-            if (any_set<WPL>(P2)) {
-                // the child is a node: push the current frame, descend
-                const uint32_t idv = row_id(row, v);
-                nodes++;
-                if (d < lds_depth) {
-                    uint32_t* f = stk + (size_t)d * SW;
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) {
-                        const uint32_t li = (uint32_t)c * 64u + lane;
-                        f[3 * li] = P[c];
-                        f[3 * li + 1] = X[c];
-                        f[3 * li + 2] = L[c];
-                    }
-                    idstk = (lane == d) ? idv : idstk;
-                } else {
-                    if (d - lds_depth >= sp.spill_levels) {
-                        if (lane == 0) atomicOr(&sp.ctl->error, kErrDepth);
-                        abort = true;
-                        break;
-                    }
-                    if (chunk == 0xffffffffu) {
-                        uint32_t ch = 0;
-                        if (lane == 0) ch = (uint32_t)atomicAdd(&sp.ctl->spill_next, 1ull);
-                        ch = bcast0(ch);
-                        if (ch >= sp.spill_chunks) {
-                            if (lane == 0) atomicOr(&sp.ctl->error, kErrSpill);
-                            abort = true;
-                            break;
-                        }
-                        chunk = ch;
-                        if (lane == 0) ctx->spill_chunk = ch;
-                    }
-                    uint32_t* fs = sp.spill + ((size_t)chunk * sp.spill_levels + (d - lds_depth)) * SPW;
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) {
-                        const uint32_t li = (uint32_t)c * 64u + lane;
-                        fs[4 * li] = P[c];
-                        fs[4 * li + 1] = X[c];
-                        fs[4 * li + 2] = L[c];
-                        fs[4 * li + 3] = idv;
-                    }
-                    if (lane == 0) ctx->spills += 1;
-                }
-                d++;
-                uint32_t mi[WPL];
-                bit_mask<WPL>(idv, lane_lo, mi);
-#pragma unroll
-                for (int c = 0; c < WPL; c++) {
-                    Rb[c] |= mi[c];
-                    P[c] = P2[c];
-                    X[c] = X2[c];
-                }
-                // step 9: pivot = first of X if X is non-empty, else first of P
-                int pi = first_pos<WPL>(X, lane_lo);
-                if (pi < 0) pi = first_pos<WPL>(P, lane_lo);
-                // step 10: L = P \ N(p)
-                const uint32_t so = (uint32_t)pi * rs4;
-#pragma unroll
-                for (int c = 0; c < WPL; c++)
-                    L[c] = P[c] & ~(uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rows, (int)voff[c], (int)so, 0);
-            } else if (!any_set<WPL>(X2)) {
-                // P' and X' empty: R u {v} is maximal.  R is the bitset Rb over
-                // input ids; its non-empty 16-bit halves, in lane order, are the
-                // clique's sorted ids.
-                const uint32_t idv = row_id(row, v);
-                if (nent == 64u || used + 2u * 64u * WPL > kCliqueSlots) {
-                    acc = cold_flush(spp, wl, cent, nent, hoff_lo, hoff_hi, acc);
-                    nent = 0;
-                    used = 0;
-                }
-                uint32_t mi[WPL];
-                bit_mask<WPL>(idv, lane_lo, mi);
-                const uint32_t start = used;
-#pragma unroll
-                for (int c = 0; c < WPL; c++) {
-                    const uint32_t cw = Rb[c] | mi[c];
-                    const uint32_t lo = cw & 0xffffu, hi = cw >> 16;
-                    const uint64_t blo = ballot(lo != 0u), bhi = ballot(hi != 0u);
-                    const uint32_t below =
-                        __builtin_amdgcn_mbcnt_hi((uint32_t)(blo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)blo, 0u)) +
-                        __builtin_amdgcn_mbcnt_hi((uint32_t)(bhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bhi, 0u));
-                    const uint32_t plo = used + below;
-                    const uint32_t phi = plo + (lo != 0u ? 1u : 0u);
-                    const uint32_t hw = (((uint32_t)c * 64u + lane) << 1);
-                    *(lo != 0u ? buf + plo : trash + lane) = (hw << 16) | lo;
-                    *(hi != 0u ? buf + phi : trash + lane) = ((hw + 1u) << 16) | hi;
-                    used += (uint32_t)__builtin_popcountll(blo) + (uint32_t)__builtin_popcountll(bhi);
-                }
-                cent = (lane == nent) ? ((start << 16) | (used - start)) : cent;
-                nent++;
-            }
-
-            if (--budget == 0u) {
-                budget = ci;
-                // Look at the siblings (LDS only); call the out-of-line handler
-                // only when there is something to do.
-                if (lane == 0) {
-                    __hip_atomic_fetch_add(&ctx->nodes, (unsigned long long)nodes, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    __hip_atomic_fetch_add(&ctx->children, (unsigned long long)kids, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
-                }
-                nodes = 0;
-                kids = 0;
-                const uint32_t busy = bcast0(lds_ld(&hdr->busy));
-                const uint32_t lqn = bcast0(lds_ld(&hdr->lq_n));
-                const uint32_t dn = bcast0(lds_ld(&hdr->done));
-                const uint32_t asked = bcast0(lds_ld(&hdr->req));
-                uint32_t tk = 0;
-                if (lane == 0)
-                    tk = __hip_atomic_fetch_add(&hdr->ticks, ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                tk = bcast0(tk);
-                const uint32_t refresh = (tk / refresh_children) != ((tk + ci) / refresh_children);
-                if (dn) {
-                    abort = true;
-                    break;
-                }
-                if (refresh || asked || lqn == 0u || (lqn < kLocalSlots && NW - busy > lqn)) {
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) {
-                        const uint32_t li = (uint32_t)c * 64u + lane;
-                        cur[3 * li] = P[c];
-                        cur[3 * li + 1] = X[c];
-                        cur[3 * li + 2] = L[c];
-                    }
-                    LaneBits<WPL> rbb;
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) rbb.w[c] = Rb[c];
-                    if (bcast0(cold_check<WPL>(spp, smem, wl, d, W, g, rbb, idstk, t_start, refresh))) {
-                        abort = true;
-                        break;
-                    }
-#pragma unroll
-                    for (int c = 0; c < WPL; c++) {
-                        const uint32_t li = (uint32_t)c * 64u + lane;
-                        const uint32_t l0 = cur[3 * li + 2];
-                        L[c] = live[c] ? l0 : 0u;
-                    }
-                    chunk = bcast0(ctx->spill_chunk);
-                }
-            }
+            if (abort) break;
         }
+        if (bcast0(ctx->nent) != 0u) cold_flush(spp, wl, sp.graphs[g].hist_off);
+        if (lane == 0) ctx->busy += wall_clock64() - t_unit;
 
         // ---- unit finished ----
-        if (nent) acc = cold_flush(spp, wl, cent, nent, hoff_lo, hoff_hi, acc);
-        if (lane == 0) {
-            ctx->nodes += nodes;
-            ctx->children += kids;
-        }
         set_state(kWaveIdle);
         if (!wg_lock(hdr, lane, t_start, sp.watchdog_ticks)) {
             give_up();
@@ -1451,12 +1652,16 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         wg_unlock(hdr, lane);
         if (abort) break;
     }
-    cold_fold(spp, wl, acc);
+    cold_fold(spp, wl);
     set_state(kWaveExited);
     if (lane == 0) {
         if (ctx->units) atomicAdd(&sp.ctl->units, ctx->units);
         if (ctx->donations) atomicAdd(&sp.ctl->donations, ctx->donations);
         if (ctx->spills) atomicAdd(&sp.ctl->spill_levels_written, ctx->spills);
+        if (ctx->checks) atomicAdd(&sp.ctl->checks, (unsigned long long)ctx->checks);
+        if (ctx->flushes) atomicAdd(&sp.ctl->flushes, (unsigned long long)ctx->flushes);
+        atomicAdd(&sp.ctl->busy_ticks, ctx->busy);
+        atomicAdd(&sp.ctl->run_ticks, (unsigned long long)(wall_clock64() - t_start));
     }
 }
 

@@ -21,9 +21,10 @@ constexpr uint32_t kWgHdrWords = 16;
 constexpr uint32_t kLocalSlots = 8;
 // LDS words of a wavefront before its frames: histogram (kHistLds u64), the
 // clique buffer (kCliqueSlots words), 64 words that absorb the stores of lanes
-// with nothing to store, and a 32-word context block.  Then come the stack
-// window, the slot of the current frame and some slack (lds_frame_words).
-constexpr uint32_t kWaveFixedWords = kHistLds * 2 + kCliqueSlots + 64 + 32;
+// with nothing to store, a 32-word context block and a 128-word save area for
+// the search loop's lane registers.  Then come the stack window, the slot of
+// the current frame and some slack (lds_frame_words).
+constexpr uint32_t kWaveFixedWords = kHistLds * 2 + kCliqueSlots + 64 + 32 + 128;
 
 // Wavefront-lane layout of the search: one 32-bit word per lane and chunk.
 // A graph with w32 + 1 <= 64 row words (n <= 2016) uses one chunk, larger ones
@@ -31,13 +32,18 @@ constexpr uint32_t kWaveFixedWords = kHistLds * 2 + kCliqueSlots + 64 + 32;
 constexpr uint32_t kOneChunkMaxW32 = 63;
 inline uint32_t search_chunks(uint32_t max_w32) { return max_w32 <= kOneChunkMaxW32 ? 1u : 2u; }
 
-// LDS stack frame (P, X, L interleaved per lane, 12 bytes a lane): words per
-// frame, and the slack after the last frame that absorbs the stores of lanes
-// past the row.
-inline uint32_t lds_frame_words(uint32_t max_w32) { return search_chunks(max_w32) == 1 ? 3u * max_w32 : 384u; }
+// LDS stack frame (P, X, L and the row of the frame's next candidate,
+// interleaved per lane, 16 bytes a lane): words per frame, and the slack after
+// the last frame that absorbs the accesses of lanes past the row.  With one
+// chunk a frame spans lanes 0..max_w32, so that the row's input-id word (lane
+// w32) is kept.
+inline uint32_t lds_frame_words(uint32_t max_w32)
+{
+    return search_chunks(max_w32) == 1 ? 4u * (max_w32 + 1u) : 512u;
+}
 inline uint32_t lds_slack_words(uint32_t max_w32)
 {
-    return search_chunks(max_w32) == 1 ? 3u * (64u - max_w32) : 0u;
+    return search_chunks(max_w32) == 1 ? 4u * (63u - max_w32) : 0u;
 }
 // Spill frame in HBM: (P, X, L, child id) per lane, 16 bytes a lane, all lanes.
 inline uint32_t spill_frame_words(uint32_t max_w32) { return 256u * search_chunks(max_w32); }
@@ -75,7 +81,8 @@ struct QueueCtl {
     unsigned long long spill_next;           // next free chunk of the spill pool
     unsigned long long spill_levels_written; // stack levels stored in HBM
     unsigned long long vcursor, ocursor;     // enumerate output cursors
-    unsigned long long pad_s[2];
+    unsigned long long checks, flushes;      // suspensions of the search loop, by reason
+    unsigned long long busy_ticks, run_ticks; // wall-clock ticks on units / from start to exit, all wavefronts
 };
 
 // Mailbox of one search workgroup in HBM.  A workgroup out of work asks one

@@ -57,6 +57,7 @@ struct DeviceInfo {
     int device = -1;
     int cus = 0;
     size_t lds_per_block = 0;
+    size_t lds_per_cu = 0;
     int wall_khz = 0;
 };
 
@@ -79,6 +80,8 @@ int device_info(DeviceInfo* out)
         g_dev.device = dev;
         g_dev.cus = prop.multiProcessorCount;
         g_dev.lds_per_block = prop.sharedMemPerBlock;
+        g_dev.lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                                 : prop.sharedMemPerBlock;
         if (hipDeviceGetAttribute(&g_dev.wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
             g_dev.wall_khz = 0;
         g_dev.ok = 1;
@@ -303,6 +306,10 @@ struct mce_graph_s {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float prepare_ms = 0.f;
     bool prepared_timed = false;
+    // learned from reruns, kept for the next solves of this handle: spill
+    // chunks for every wavefront, and chunks of the full stack depth
+    uint32_t spill_floor = 0;
+    bool spill_full_depth = false;
     ~mce_graph_s()
     {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -322,6 +329,8 @@ size_t out_bytes(const mce_graph_s* h)
 // these workloads; a deeper one stops with kErrDepth and reruns with chunks of
 // the full depth n - lds_depth.
 constexpr uint32_t kSpillLevelsFirst = 64;
+// Bounds of the LDS stack window chosen when the caller sets none.
+constexpr uint32_t kAutoDepth = 12, kMinAutoDepth = 4;
 
 int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32_t blocks_cap = 0,
              bool full_depth = false)
@@ -335,12 +344,29 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
     c.slot_words = lds_frame_words(c.w32cap);
     const uint32_t slack = lds_slack_words(c.w32cap);
-    uint32_t depth = o.lds_depth >= 0 ? (uint32_t)std::min<int64_t>(o.lds_depth, 64) : 12u;
-    // keep a workgroup within the LDS limit
     const uint32_t rec_words = kRecHeader + 4 * c.w32cap;
+    auto wave_words = [&](uint32_t dep) {
+        const uint32_t wl = kWaveFixedWords + (dep + 1) * c.slot_words + slack;
+        return (wl + 3u) & ~3u; // frames on 16-byte boundaries
+    };
+    uint32_t depth;
+    if (o.lds_depth >= 0) {
+        depth = (uint32_t)std::min<int64_t>(o.lds_depth, 64);
+    } else {
+        // The deepest window, up to kAutoDepth levels, with which the
+        // workgroups that the registers allow on a CU also fit in its LDS;
+        // frames below it go to the spill pool.
+        int by_regs = 0;
+        HIP_TRY(search_occupancy(h->max_w32, c.wpb, 0, &by_regs));
+        const uint32_t wgs = (uint32_t)std::max(by_regs, 1);
+        depth = kAutoDepth;
+        while (depth > kMinAutoDepth &&
+               (uint64_t)search_lds_bytes(wave_words(depth), rec_words, c.wpb) * wgs > di.lds_per_cu)
+            depth--;
+    }
+    // keep a workgroup within the LDS limit
     for (;;) {
-        uint32_t wl = kWaveFixedWords + (depth + 1) * c.slot_words + slack;
-        wl = (wl + 1u) & ~1u;
+        const uint32_t wl = wave_words(depth);
         if (search_lds_bytes(wl, rec_words, c.wpb) <= di.lds_per_block || (depth == 0 && c.wpb == 1)) {
             c.wave_lds_words = wl;
             break;
@@ -424,7 +450,7 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
     const bool have_clock = device_info(&di) == MCE_OK && di.wall_khz > 0;
     if (o.watchdog_ms > 0 && have_clock) sp.watchdog_ticks = (uint64_t)o.watchdog_ms * (uint64_t)di.wall_khz;
     // a busy workgroup looks at its mailbox every refresh_children children
-    sp.refresh_children = o.refresh_children > 0 ? (uint32_t)o.refresh_children : 128u;
+    sp.refresh_children = o.refresh_children > 0 ? (uint32_t)o.refresh_children : sp.check_interval;
     if (sp.refresh_children < sp.check_interval) sp.refresh_children = sp.check_interval;
     // an idle workgroup reads the end-of-search counter every poll_iters looks
     sp.poll_iters = 8;
@@ -522,8 +548,8 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
 {
     int rc = ensure_events(g);
     if (rc != MCE_OK) return rc;
-    uint32_t floor = 0;
-    bool full_depth = false;
+    uint32_t floor = g->spill_floor;
+    bool full_depth = g->spill_full_depth;
     for (int attempt = 0; attempt < 4; attempt++) {
         LaunchCfg c;
         if ((rc = make_cfg(g, &c, floor, blocks_cap, full_depth)) != MCE_OK) return rc;
@@ -591,6 +617,8 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         if (ctl.error & (kErrSpill | kErrDepth)) {
             if (ctl.error & kErrSpill) floor = c.blocks * c.wpb; // one chunk for every wavefront
             if (ctl.error & kErrDepth) full_depth = true;
+            g->spill_floor = floor;
+            g->spill_full_depth = full_depth;
             continue;
         }
         if (ctl.error) return MCE_E_DEVICE;
@@ -612,6 +640,10 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         st.donations = ctl.donations;
         st.units = ctl.units;
         st.spills = ctl.spill_levels_written;
+        st.checks = ctl.checks;
+        st.flushes = ctl.flushes;
+        st.attempts = (uint32_t)attempt + 1u;
+        st.busy_frac = ctl.run_ticks ? (double)ctl.busy_ticks / (double)ctl.run_ticks : 0.0;
         t_stats = st;
         return MCE_OK;
     }

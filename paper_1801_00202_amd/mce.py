@@ -88,6 +88,11 @@ class Stats(ctypes.Structure):
         ("donations", ctypes.c_uint64),
         ("units", ctypes.c_uint64),
         ("spills", ctypes.c_uint64),
+        ("checks", ctypes.c_uint64),
+        ("flushes", ctypes.c_uint64),
+        ("attempts", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("busy_frac", ctypes.c_double),
     ]
 
 
