@@ -88,19 +88,22 @@ def copy_probe(mib: int, reps: int) -> None:
                       "GB_per_s": 8 * n / dt / 1e9}))
 
 
-def batched(mce, synth, np, reps: int) -> dict:
+def batched(mce, synth, np, reps: int, tune: bool) -> dict:
     """4096 graphs (n ~ U{32..512}, p ~ U[0.1, 0.9], E[mu] <= 1e6, base seed 0)
-    in one handle and one persistent launch, against the same graphs solved
-    one by one (the plain single-graph solve)."""
+    in one handle and one persistent launch (schedule from mce_autotune,
+    replayed as a captured hipGraph), against the same graphs solved one by
+    one (the plain single-graph solve)."""
     import torch
     graphs = [synth.gnp(n, p, seed) for n, p, seed in synth.batch_mix(4096, 0)]
     b = mce.Graph(batch=graphs)
+    tuned = b.autotune(max_trials=12) if tune else None
     out = b.count()                      # warm-up, captures the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         out = b.count()
     dt = (time.perf_counter() - t0) / reps
+    device_ms = mce.last_stats()["search_us"] / 1e3
     b.release()
     cliques = sum(r["count"] for r in out)
     nodes = sum(r["nodes"] for r in out)
@@ -114,7 +117,11 @@ def batched(mce, synth, np, reps: int) -> dict:
         h.release()
     assert [r["hash_xor"] for r in plain] == [r["hash_xor"] for r in out]
     return {"workload": "4096 graphs, n ~ U{32..512}, p ~ U[0.1,0.9], E[mu] <= 1e6, base seed 0",
-            "cliques": cliques, "nodes": nodes, "ms_per_batch": dt * 1e3,
+            "autotune": None if tuned is None else {
+                k: tuned[k] for k in ("waves_per_block", "blocks", "lds_depth", "split_threshold",
+                                      "check_interval", "trials")} | {
+                "auto_solve_ms": tuned["auto_us"] / 1e3, "tuned_solve_ms": tuned["best_us"] / 1e3},
+            "cliques": cliques, "nodes": nodes, "ms_per_batch": dt * 1e3, "device_solve_ms": device_ms,
             "cliques_per_s": cliques / dt, "nodes_per_s": nodes / dt,
             "plain_ms": dt_plain * 1e3, "plain_cliques_per_s": cliques / dt_plain,
             "vs_plain": dt_plain / dt}
@@ -184,6 +191,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--no-tune", action="store_true", help="automatic schedule instead of mce_autotune's")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -206,6 +214,16 @@ def main():
     rows = synth.gnp(wl["n"], wl["p"], wl["seed"])
     d_rows = torch.from_numpy(rows.view(np.int64)).cuda()
     torch.cuda.synchronize()
+
+    # Schedule: mce_autotune on one handle of the workload graph (untimed), its
+    # choice applied as options to the timed steps, which each make a new handle.
+    tuned = None
+    if not args.no_tune:
+        g0 = mce.Graph(d_rows)
+        tuned = g0.autotune()
+        g0.release()
+        for k in ("waves_per_block", "blocks", "lds_depth", "split_threshold", "check_interval"):
+            mce.set_option(k, tuned[k])
 
     def step():
         g = mce.Graph(d_rows)
@@ -261,15 +279,20 @@ def main():
         "search_kernel_ms": k_us / 1e3,
         "prepare_ms": sum(s["prepare_us"] for s in stats) / len(stats) / 1e3,
         "launch": {"blocks": stats[0]["blocks"], "waves_per_block": stats[0]["waves_per_block"],
-                   "lds_depth": stats[0]["lds_depth"], "donations": stats[0]["donations"],
-                   "units": stats[0]["units"]},
+                   "lds_depth": stats[0]["lds_depth"], "split_threshold": None if tuned is None else
+                   tuned["split_threshold"], "check_interval": None if tuned is None else tuned["check_interval"],
+                   "donations": stats[0]["donations"], "units": stats[0]["units"],
+                   "busy_frac": stats[0]["busy_frac"], "tail_frac": stats[0]["tail_frac"]},
+        "autotune": None if tuned is None else {"trials": tuned["trials"], "auto_solve_ms": tuned["auto_us"] / 1e3,
+                                                "tuned_solve_ms": tuned["best_us"] / 1e3},
         "roofline": {"bound": "alu", "kernel": "search_kernel", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T int32 lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
                      "ops_per_launch": ops,
                      "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"]},
     }
+    mce.reset_options(watchdog_ms=120000)
     if not args.no_batch:
-        line["batched"] = batched(mce, synth, np, reps=3)
+        line["batched"] = batched(mce, synth, np, reps=3, tune=not args.no_tune)
     if not args.no_serving:
         line["serving"] = serving(mce, synth, np, args.serving_requests, warm=100)
     if not args.no_cpu_baseline:

@@ -201,6 +201,35 @@ int mce_poll(uint64_t ticket, mce_result_t *res, int32_t timeout_us);
  * already running (it then completes normally), MCE_E_INVAL if unknown. */
 int mce_cancel(uint64_t ticket);
 
+/* mce_autotune -- choose this handle's launch schedule by timing it.
+ *
+ * Times complete solves of the handle (mce_count) under candidate schedules
+ * and keeps the fastest for later calls on the handle: first the launch shape
+ * (search wavefronts per workgroup in {4, 8, 16} and workgroups per CU, each
+ * with the deepest LDS stack window that fits), then the split threshold, then
+ * the check interval, each around the best choice so far.  Every solve must
+ * reproduce the first one's count, nodes, children, dead ends, hashes and
+ * omega exactly (the schedule decides only who explores which subtree);
+ * otherwise MCE_E_DEVICE.  Options set with mce_set_option still take
+ * precedence over the tuned values.
+ *   max_trials  candidate schedules to time at most (0: 32); each is solved twice
+ *   out         optional: the kept schedule and the solve times of the
+ *               automatic and kept schedules (best of two, microseconds)
+ *   hip_stream  stream of the solves (NULL: default stream)
+ * Thread-safe per handle (takes the handle's lock).  Not an operation of the
+ * paper: a runtime aid, like the work distribution it tunes. */
+typedef struct {
+    uint32_t waves_per_block, blocks, lds_depth, split_threshold, check_interval;
+    uint32_t trials;     /* schedules timed */
+    double auto_us;      /* solve time with the automatic schedule */
+    double best_us;      /* solve time with the kept schedule */
+} mce_tune_t;
+
+int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t *out, void *hip_stream);
+
+/* Forget the tuned schedule of a handle (back to the automatic one). */
+int mce_clear_tuning(mce_graph_t g);
+
 /* Free the handle and its device memory.  NULL is accepted. */
 int mce_release(mce_graph_t g);
 
@@ -227,8 +256,10 @@ typedef struct {
     uint64_t flushes;      /* times it stopped to hash a full clique buffer */
     uint32_t attempts;     /* launches of the last call (a rerun follows an exhausted spill pool) */
     uint32_t reserved;
-    double busy_frac;      /* share of the search kernel's wavefront time spent on units (the
-                              rest is looking for work and the end of the launch) */
+    double busy_frac;      /* share of the search kernel's wavefront time spent on units */
+    double ramp_frac;      /* share spent before a wavefront's first unit */
+    double tail_frac;      /* share spent after its last unit (the rest of the idle time is
+                              spent between units, looking for work) */
 } mce_stats_t;
 
 int mce_last_stats(mce_stats_t *out);

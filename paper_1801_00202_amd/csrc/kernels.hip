@@ -331,6 +331,53 @@ __global__ void __launch_bounds__(64) order_kernel(const GraphDesc* graphs, cons
     }
 }
 
+// The same ordering with the graph's input rows staged in LDS first (when
+// they fit), so that each of the n dependent rounds reads the chosen vertex's
+// row chunk from LDS instead of waiting for a global load.
+template <int KPL>
+__global__ void __launch_bounds__(64) order_lds_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
+                                                       uint32_t* order)
+{
+    extern __shared__ uint64_t rows_l[];
+    const GraphDesc gd = graphs[blockIdx.x];
+    const uint32_t n = gd.n;
+    if (n == 0) return;
+    const uint32_t lane = lane_id();
+    const uint64_t* in = rows_in + gd.in_off;
+    const uint32_t rs = gd.rw64;
+    const uint64_t words = (uint64_t)n * rs;
+    for (uint64_t i = lane; i < words; i += 64) rows_l[i] = in[i];
+    __syncthreads();
+    const uint32_t v0 = lane * KPL;
+    const uint32_t cw = v0 >> 6, csh = v0 & 63; // word and shift of this lane's row chunk
+    const uint64_t cmask = ~0ull >> (64 - KPL);
+    uint32_t key[KPL];
+#pragma unroll
+    for (int j = 0; j < KPL; j++) {
+        const uint32_t v = v0 + (uint32_t)j;
+        uint32_t deg = 0;
+        if (v < n)
+            for (uint32_t t = 0; t < rs; t++) deg += (uint32_t)__builtin_popcountll(rows_l[(uint64_t)v * rs + t]);
+        key[j] = (v < n) ? (((deg + 1u) << 12) | (4095u - v)) : 0u;
+    }
+    uint32_t* ord = order + gd.ord_off;
+    for (uint32_t i = 0; i < n; i++) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int j = 0; j < KPL; j++) m = umax32(m, key[j]);
+        m = wave_max(m);
+        const uint32_t v = 4095u - (m & 4095u);
+        if (lane == 0) ord[i] = v;
+        const uint64_t chunk = (v0 < n) ? ((rows_l[(uint64_t)v * rs + cw] >> csh) & cmask) : 0ull;
+        const uint64_t vm = ((v / KPL) == lane) ? (1ull << (v % KPL)) : 0ull;
+#pragma unroll
+        for (int j = 0; j < KPL; j++) {
+            const bool nb = ((chunk >> j) & 1ull) && key[j] != 0u;
+            key[j] = ((vm >> j) & 1ull) ? 0u : (key[j] - (nb ? 4096u : 0u));
+        }
+    }
+}
+
 // Renumbering (Sec. 4.2): row i of the new matrix is row order[i] of the input
 // with column j taken from column order[j].  Block (i, g), one word per thread.
 __global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
@@ -625,6 +672,10 @@ struct WaveCtx {
     uint32_t checks, flushes; // suspensions of the search loop, by reason
     unsigned long long busy;  // wall-clock ticks spent on units
     uint32_t pad[2];
+};
+// Wall-clock ticks of a wavefront's first unit start and last unit end.
+struct WaveTimes {
+    unsigned long long first, last;
 };
 static_assert(sizeof(WaveCtx) == 32 * 4, "ctx size");
 
@@ -1378,6 +1429,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
 
     const uint32_t me = blockIdx.x;
     uint32_t backoff = 1, idle_iters = 0, polls = 0;
+    WaveTimes times{0, 0}; // lane 0 only
     for (;;) {
         // ================= obtain a unit =================
         // src 1: the LDS LIFO (slot lsl), 2: the pool of root units (index
@@ -1639,7 +1691,12 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
             if (abort) break;
         }
         if (bcast0(ctx->nent) != 0u) cold_flush(spp, wl, sp.graphs[g].hist_off);
-        if (lane == 0) ctx->busy += wall_clock64() - t_unit;
+        if (lane == 0) {
+            const uint64_t t_end = wall_clock64();
+            ctx->busy += t_end - t_unit;
+            if (times.first == 0) times.first = t_unit;
+            times.last = t_end;
+        }
 
         // ---- unit finished ----
         set_state(kWaveIdle);
@@ -1660,8 +1717,11 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         if (ctx->spills) atomicAdd(&sp.ctl->spill_levels_written, ctx->spills);
         if (ctx->checks) atomicAdd(&sp.ctl->checks, (unsigned long long)ctx->checks);
         if (ctx->flushes) atomicAdd(&sp.ctl->flushes, (unsigned long long)ctx->flushes);
+        const uint64_t t_exit = wall_clock64();
         atomicAdd(&sp.ctl->busy_ticks, ctx->busy);
-        atomicAdd(&sp.ctl->run_ticks, (unsigned long long)(wall_clock64() - t_start));
+        atomicAdd(&sp.ctl->run_ticks, (unsigned long long)(t_exit - t_start));
+        atomicAdd(&sp.ctl->ramp_ticks, (unsigned long long)((times.first ? times.first : t_exit) - t_start));
+        atomicAdd(&sp.ctl->tail_ticks, (unsigned long long)(times.first ? t_exit - times.last : 0));
     }
 }
 
@@ -1680,10 +1740,43 @@ hipError_t launch_validate(const uint64_t* rows, uint32_t n, uint32_t rw, unsign
     return hipGetLastError();
 }
 
+static hipError_t ensure_order_attr()
+{
+    // Allow the staged ordering kernels the full LDS of a workgroup once per process.
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        int dev = 0, lds = 0;
+        err = hipGetDevice(&dev);
+        if (err == hipSuccess) err = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        const void* ks[] = {(const void*)order_lds_kernel<8>, (const void*)order_lds_kernel<16>,
+                            (const void*)order_lds_kernel<32>};
+        for (const void* k : ks)
+            if (err == hipSuccess) err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    });
+    return err;
+}
+
 hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
                         const uint64_t* rows_in, uint32_t* order, hipStream_t s)
 {
     (void)hipGetLastError(); // report only this call's launch errors
+    // rows staged in LDS when the largest graph's fit in a workgroup's LDS
+    const uint64_t lds = (uint64_t)max_n * ((max_n + 63u) / 64u) * 8u;
+    int dev = 0, lds_max = 0;
+    if (max_n <= 2048 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        lds <= (uint64_t)lds_max) {
+        hipError_t e = ensure_order_attr();
+        if (e != hipSuccess) return e;
+        if (max_n <= 512)
+            hipLaunchKernelGGL(order_lds_kernel<8>, dim3(num_graphs), dim3(64), lds, s, graphs, rows_in, order);
+        else if (max_n <= 1024)
+            hipLaunchKernelGGL(order_lds_kernel<16>, dim3(num_graphs), dim3(64), lds, s, graphs, rows_in, order);
+        else
+            hipLaunchKernelGGL(order_lds_kernel<32>, dim3(num_graphs), dim3(64), lds, s, graphs, rows_in, order);
+        return hipGetLastError();
+    }
     if (max_n <= 512)
         hipLaunchKernelGGL(order_kernel<8>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
     else if (max_n <= 1024)

@@ -83,6 +83,7 @@ struct QueueCtl {
     unsigned long long vcursor, ocursor;     // enumerate output cursors
     unsigned long long checks, flushes;      // suspensions of the search loop, by reason
     unsigned long long busy_ticks, run_ticks; // wall-clock ticks on units / from start to exit, all wavefronts
+    unsigned long long ramp_ticks, tail_ticks; // before the first unit / after the last one
 };
 
 // Mailbox of one search workgroup in HBM.  A workgroup out of work asks one

@@ -299,8 +299,10 @@ struct mce_graph_s {
     DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params, d_sub;
     HostPinned h_params; // staging of the search parameters (stable for graph replays)
     HostPinned h_out; // results | ctl | hist, copied back in one go
-    LaunchCfg cfg;
-    bool cfg_valid = false;
+    // launch choices fixed for this handle by mce_autotune (0: automatic)
+    struct Tune {
+        uint32_t wpb = 0, wgs_per_cu = 0, split_threshold = 0, check_interval = 0;
+    } tune;
     hipGraphExec_t graph_exec = nullptr;
     LaunchCfg graph_cfg;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -340,7 +342,9 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     if (rc != MCE_OK) return rc;
     const Options o = options();
     LaunchCfg c;
-    c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16) : 8u;
+    // an explicit option wins, then the handle's tuned choice, then the default
+    c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16)
+                                  : (h->tune.wpb ? h->tune.wpb : 8u);
     c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
     c.slot_words = lds_frame_words(c.w32cap);
     const uint32_t slack = lds_slack_words(c.w32cap);
@@ -358,7 +362,8 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         // frames below it go to the spill pool.
         int by_regs = 0;
         HIP_TRY(search_occupancy(h->max_w32, c.wpb, 0, &by_regs));
-        const uint32_t wgs = (uint32_t)std::max(by_regs, 1);
+        uint32_t wgs = (uint32_t)std::max(by_regs, 1);
+        if (o.blocks <= 0 && h->tune.wgs_per_cu) wgs = std::min(wgs, h->tune.wgs_per_cu);
         depth = kAutoDepth;
         while (depth > kMinAutoDepth &&
                (uint64_t)search_lds_bytes(wave_words(depth), rec_words, c.wpb) * wgs > di.lds_per_cu)
@@ -382,12 +387,15 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         int bpc = 0;
         HIP_TRY(search_occupancy(h->max_w32, c.wpb, lds_bytes, &bpc));
         if (bpc < 1) bpc = 1;
+        if (h->tune.wgs_per_cu) bpc = std::min<int>(bpc, (int)h->tune.wgs_per_cu);
         c.blocks = (uint32_t)di.cus * (uint32_t)bpc;
     }
     if (blocks_cap && c.blocks > blocks_cap) c.blocks = blocks_cap;
     const uint32_t waves = c.blocks * c.wpb;
-    c.split_threshold = o.split_threshold > 0 ? (uint32_t)o.split_threshold : 12u;
-    c.check_interval = next_pow2(o.check_interval > 0 ? (uint64_t)o.check_interval : 32u);
+    c.split_threshold = o.split_threshold > 0 ? (uint32_t)o.split_threshold
+                                              : (h->tune.split_threshold ? h->tune.split_threshold : 12u);
+    c.check_interval = next_pow2(o.check_interval > 0 ? (uint64_t)o.check_interval
+                                                      : (h->tune.check_interval ? h->tune.check_interval : 32u));
     uint64_t cap = o.queue_cap > 0 ? (uint64_t)o.queue_cap
                                    : std::max<uint64_t>({(uint64_t)waves * 2u, (uint64_t)h->num_graphs * 2u, 1024u});
     cap = std::max<uint64_t>(cap, (uint64_t)h->num_graphs + 1u);
@@ -644,6 +652,8 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         st.flushes = ctl.flushes;
         st.attempts = (uint32_t)attempt + 1u;
         st.busy_frac = ctl.run_ticks ? (double)ctl.busy_ticks / (double)ctl.run_ticks : 0.0;
+        st.ramp_frac = ctl.run_ticks ? (double)ctl.ramp_ticks / (double)ctl.run_ticks : 0.0;
+        st.tail_frac = ctl.run_ticks ? (double)ctl.tail_ticks / (double)ctl.run_ticks : 0.0;
         t_stats = st;
         return MCE_OK;
     }
@@ -989,6 +999,128 @@ int mce_enumerate(mce_graph_t g, uint32_t* verts, uint64_t verts_cap, uint64_t* 
         res->status = MCE_E_TRUNCATED;
         return MCE_E_TRUNCATED;
     }
+    return MCE_OK;
+}
+
+int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t* out, void* hip_stream)
+{
+    if (!g) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    if (max_trials == 0) max_trials = 32;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const uint32_t ng = g->num_graphs;
+    std::vector<mce_result_t> ref(ng), cur(ng);
+    bool have_ref = false;
+    uint32_t trials = 0;
+    // One candidate: the best of two timed solves (HIP events around the
+    // whole solve); every solve must give exactly the results of the first.
+    auto trial = [&](const mce_graph_s::Tune& t, double* us) -> int {
+        g->tune = t;
+        double best = 1e300;
+        for (int r = 0; r < 2; r++) {
+            for (auto& x : cur) std::memset(&x, 0, sizeof(x));
+            const int e = run_solve(g, 0, UINT64_MAX, cur.data(), s, nullptr, 0, nullptr, 0, nullptr, false);
+            if (e != MCE_OK) return e;
+            best = std::min(best, t_stats.search_us);
+            if (!have_ref) {
+                ref = cur;
+                have_ref = true;
+            }
+            for (uint32_t i = 0; i < ng; i++) {
+                const mce_result_t &a = ref[i], &b = cur[i];
+                if (a.count != b.count || a.nodes != b.nodes || a.children != b.children ||
+                    a.dead_ends != b.dead_ends || a.hash_xor != b.hash_xor || a.hash_sum != b.hash_sum ||
+                    a.omega != b.omega)
+                    return MCE_E_DEVICE; // a schedule changed a result: a bug, not a tuning choice
+            }
+        }
+        trials++;
+        *us = best;
+        return MCE_OK;
+    };
+    // The automatic choice first, written out as a tuned one.
+    mce_graph_s::Tune best_t;
+    double best_us = 0, auto_us = 0;
+    if ((rc = trial(best_t, &auto_us)) != MCE_OK) return rc;
+    {
+        LaunchCfg c;
+        if ((rc = make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth)) != MCE_OK) return rc;
+        DeviceInfo di;
+        if ((rc = device_info(&di)) != MCE_OK) return rc;
+        best_t.wpb = c.wpb;
+        best_t.wgs_per_cu = std::max<uint32_t>(c.blocks / (uint32_t)std::max(di.cus, 1), 1u);
+        best_t.split_threshold = c.split_threshold;
+        best_t.check_interval = c.check_interval;
+    }
+    best_us = auto_us;
+    auto consider = [&](mce_graph_s::Tune t) -> int {
+        if (trials >= max_trials) return MCE_OK;
+        double us = 0;
+        const int e = trial(t, &us);
+        if (e != MCE_OK) return e;
+        if (us < best_us) {
+            best_us = us;
+            best_t = t;
+        }
+        return MCE_OK;
+    };
+    // 1. Launch shape: wavefronts per workgroup and workgroups per CU (the
+    //    LDS stack window is then the deepest that fits).
+    const mce_graph_s::Tune shape0 = best_t;
+    for (uint32_t wpb : {4u, 8u, 16u}) {
+        int by_regs = 0;
+        HIP_TRY(search_occupancy(g->max_w32, wpb, 0, &by_regs));
+        for (uint32_t k = 1; k <= (uint32_t)std::min(by_regs, 4); k++) {
+            if (wpb == shape0.wpb && k == shape0.wgs_per_cu) continue;
+            mce_graph_s::Tune t = shape0;
+            t.wpb = wpb;
+            t.wgs_per_cu = k;
+            g->tune = t;
+            LaunchCfg c;
+            if (make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth) != MCE_OK || c.lds_depth < 2 ||
+                c.wpb != wpb)
+                continue; // too little LDS for a useful stack window
+            if ((rc = consider(t)) != MCE_OK) return rc;
+        }
+    }
+    // 2. Split threshold, 3. check interval, each around the best so far.
+    const mce_graph_s::Tune split0 = best_t;
+    for (uint32_t st : {6u, 12u, 20u, 32u}) {
+        if (st == split0.split_threshold) continue;
+        mce_graph_s::Tune t = split0;
+        t.split_threshold = st;
+        if ((rc = consider(t)) != MCE_OK) return rc;
+    }
+    const mce_graph_s::Tune ci0 = best_t;
+    for (uint32_t ci : {16u, 32u, 64u}) {
+        if (ci == ci0.check_interval) continue;
+        mce_graph_s::Tune t = ci0;
+        t.check_interval = ci;
+        if ((rc = consider(t)) != MCE_OK) return rc;
+    }
+    g->tune = best_t;
+    if (out) {
+        LaunchCfg c;
+        if ((rc = make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth)) != MCE_OK) return rc;
+        out->waves_per_block = c.wpb;
+        out->blocks = c.blocks;
+        out->lds_depth = c.lds_depth;
+        out->split_threshold = c.split_threshold;
+        out->check_interval = c.check_interval;
+        out->trials = trials;
+        out->auto_us = auto_us;
+        out->best_us = best_us;
+    }
+    return MCE_OK;
+}
+
+int mce_clear_tuning(mce_graph_t g)
+{
+    if (!g) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->tune = mce_graph_s::Tune();
     return MCE_OK;
 }
 

@@ -93,13 +93,28 @@ class Stats(ctypes.Structure):
         ("attempts", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
         ("busy_frac", ctypes.c_double),
+        ("ramp_frac", ctypes.c_double),
+        ("tail_frac", ctypes.c_double),
+    ]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [
+        ("waves_per_block", ctypes.c_uint32),
+        ("blocks", ctypes.c_uint32),
+        ("lds_depth", ctypes.c_uint32),
+        ("split_threshold", ctypes.c_uint32),
+        ("check_interval", ctypes.c_uint32),
+        ("trials", ctypes.c_uint32),
+        ("auto_us", ctypes.c_double),
+        ("best_us", ctypes.c_double),
     ]
 
 
 EXPORTS = (
     "mce_prepare", "mce_num_graphs", "mce_get_order", "mce_root_branches", "mce_count",
     "mce_count_range", "mce_count_subproblem", "mce_enumerate", "mce_submit", "mce_poll", "mce_cancel", "mce_release",
-    "mce_strerror", "mce_set_option", "mce_get_option", "mce_last_stats",
+    "mce_strerror", "mce_set_option", "mce_get_option", "mce_last_stats", "mce_autotune", "mce_clear_tuning",
 )
 
 _LIB = None
@@ -140,6 +155,8 @@ def _lib():
         lib.mce_set_option.argtypes = [i32, ctypes.c_int64]
         lib.mce_get_option.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
         lib.mce_last_stats.argtypes = [ctypes.POINTER(Stats)]
+        lib.mce_autotune.argtypes = [vp, u32, ctypes.POINTER(Tune), vp]
+        lib.mce_clear_tuning.argtypes = [vp]
         for name in EXPORTS:
             if name != "mce_strerror":
                 getattr(lib, name).restype = i32
@@ -174,9 +191,9 @@ def _new_result(n: int):
 
 
 def _to_dict(r: Result, hist: np.ndarray) -> dict:
-    h = [int(x) for x in hist]
-    while len(h) > 1 and h[-1] == 0:
-        h.pop()
+    # the histogram without trailing zeros (at least one entry)
+    nz = np.flatnonzero(hist)
+    h = hist[:max(int(nz[-1]) + 1 if nz.size else 1, 1)].tolist()
     return {
         "count": int(r.count), "nodes": int(r.nodes), "children": int(r.children),
         "dead_ends": int(r.dead_ends), "hash_xor": int(r.hash_xor), "hash_sum": int(r.hash_sum),
@@ -264,13 +281,17 @@ class Graph:
         """Single graph: a result dict.  Batch: a list of result dicts."""
         k = len(self._n)
         arr = (Result * k)()
-        hists = []
+        # one histogram buffer for all graphs, each result pointing at its part
+        lens = np.asarray(self._n, dtype=np.int64) + 1
+        offs = np.concatenate(([0], np.cumsum(lens)))
+        buf = np.zeros(int(offs[-1]), dtype=np.uint64)
+        base = buf.ctypes.data
+        p64 = ctypes.POINTER(ctypes.c_uint64)
         for i in range(k):
-            r, h = _new_result(self._n[i])
-            arr[i] = r
-            hists.append(h)
+            arr[i].hist_len = int(lens[i])
+            arr[i].hist = ctypes.cast(base + 8 * int(offs[i]), p64)
         _check(_lib().mce_count(self._h, arr, _stream_ptr(stream)), "mce_count")
-        out = [_to_dict(arr[i], hists[i]) for i in range(k)]
+        out = [_to_dict(arr[i], buf[offs[i]:offs[i + 1]]) for i in range(k)]
         return out[0] if k == 1 else out
 
     def count_range(self, first: int, last: int, stream=None) -> dict:
@@ -321,6 +342,17 @@ class Graph:
             raise MceError(rc, "mce_enumerate")
         res["truncated"] = rc == E_TRUNCATED
         return res, verts, offsets
+
+    def autotune(self, max_trials: int = 0, stream=None) -> dict:
+        """mce_autotune: time candidate schedules on this handle and keep the
+        fastest (results must agree exactly across all of them)."""
+        t = Tune()
+        _check(_lib().mce_autotune(self._h, int(max_trials), ctypes.byref(t), _stream_ptr(stream)),
+               "mce_autotune")
+        return {f: getattr(t, f) for f, _ in Tune._fields_}
+
+    def clear_tuning(self):
+        _check(_lib().mce_clear_tuning(self._h), "mce_clear_tuning")
 
     def release(self):
         if self._h:

@@ -134,6 +134,15 @@ def test_null_handles(lib, mce):
     assert lib.mce_poll(1, None, 0) == mce.E_INVAL
     assert lib.mce_release(None) == mce.OK
     assert lib.mce_last_stats(None) == mce.E_INVAL
+    assert lib.mce_autotune(None, 0, None, None) == mce.E_INVAL
+    assert lib.mce_clear_tuning(None) == mce.E_INVAL
+
+
+def test_tune_and_stats_struct_layout(mce):
+    # five u32 choices, trials, two doubles
+    assert ctypes.sizeof(mce.Tune) == 6 * 4 + 2 * 8
+    # three doubles, four u32, five u64, two u32, three doubles
+    assert ctypes.sizeof(mce.Stats) == 3 * 8 + 4 * 4 + 5 * 8 + 2 * 4 + 3 * 8
 
 
 def test_options(lib, mce):

@@ -201,3 +201,26 @@ def test_serving_alone_equals_mix(mce, orc):
         same(res, orc.greedy(r))
     for h in handles:
         h.release()
+
+
+@pytest.mark.parametrize("n,p,seed", [(200, 0.5, 21), (120, 0.75, 22)])
+def test_autotune_keeps_results(mce, orc, n, p, seed):
+    """mce_autotune times candidate schedules; the kept one, and every one it
+    timed, must give the oracle's results exactly (the library checks the
+    latter itself and fails with MCE_E_DEVICE otherwise)."""
+    rows = synth.gnp(n, p, seed)
+    ref = orc.greedy(rows)
+    g = mce.Graph(rows)
+    try:
+        t = g.autotune(max_trials=10)
+        assert 1 <= t["trials"] <= 10
+        assert t["waves_per_block"] in (4, 8, 16) and t["blocks"] >= 1 and t["lds_depth"] >= 2
+        assert t["split_threshold"] >= 1 and t["check_interval"] >= 1
+        assert 0 < t["best_us"] <= t["auto_us"]
+        same(g.count(), ref)
+        st = mce.last_stats()
+        assert st["waves_per_block"] == t["waves_per_block"] and st["blocks"] == t["blocks"]
+        g.clear_tuning()
+        same(g.count(), ref)
+    finally:
+        g.release()
