@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="automatic schedule instead of mce_autotune's")
+    ap.add_argument("--opts", default="", metavar="K=V,...",
+                    help="fixed schedule (library options such as waves_per_block=8,blocks=512); no tuning")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -218,7 +220,13 @@ def main():
     # Schedule: mce_autotune on one handle of the workload graph (untimed), its
     # choice applied as options to the timed steps, which each make a new handle.
     tuned = None
-    if not args.no_tune:
+    if args.opts:
+        fixed = {k: int(v) for k, v in (kv.split("=") for kv in args.opts.split(","))}
+        for k, v in fixed.items():
+            mce.set_option(k, v)
+        tuned = {"split_threshold": fixed.get("split_threshold"), "check_interval": fixed.get("check_interval"),
+                 "fixed": fixed}
+    elif not args.no_tune:
         g0 = mce.Graph(d_rows)
         tuned = g0.autotune()
         g0.release()
@@ -283,8 +291,9 @@ def main():
                    tuned["split_threshold"], "check_interval": None if tuned is None else tuned["check_interval"],
                    "donations": stats[0]["donations"], "units": stats[0]["units"],
                    "busy_frac": stats[0]["busy_frac"], "tail_frac": stats[0]["tail_frac"]},
-        "autotune": None if tuned is None else {"trials": tuned["trials"], "auto_solve_ms": tuned["auto_us"] / 1e3,
-                                                "tuned_solve_ms": tuned["best_us"] / 1e3},
+        "autotune": None if tuned is None or "fixed" in tuned else {
+            "trials": tuned["trials"], "auto_solve_ms": tuned["auto_us"] / 1e3, "tuned_solve_ms": tuned["best_us"] / 1e3},
+        "schedule_fixed": None if tuned is None else tuned.get("fixed"),
         "roofline": {"bound": "alu", "kernel": "search_kernel", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T int32 lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
                      "ops_per_launch": ops,
