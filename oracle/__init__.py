@@ -80,6 +80,7 @@ def _load():
         for name in ("orc_greedy", "orc_tomita", "orc_brute"):
             getattr(lib, name).argtypes = [u32, p64, u32, pres]
         lib.orc_greedy_range.argtypes = [u32, p64, u32, u64, u64, pres]
+        lib.orc_solve_rule.argtypes = [u32, p64, u32, i32, pres]
         lib.orc_greedy_mt.argtypes = [u32, p64, u32, i32, pres]
         lib.orc_greedy_range_mt.argtypes = [u32, p64, u32, u64, u64, i32, pres]
         lib.orc_root_branches.argtypes = [u32, p64, u32, p64]
@@ -87,7 +88,7 @@ def _load():
         lib.orc_subproblem.argtypes = [u32, p64, u32, i32, p32, p32, u32, p32, u32, p32, u32, pres]
         for name in ("orc_order", "orc_greedy", "orc_tomita", "orc_brute", "orc_greedy_range",
                      "orc_greedy_mt", "orc_greedy_range_mt", "orc_root_branches",
-                     "orc_greedy_list", "orc_subproblem"):
+                     "orc_greedy_list", "orc_subproblem", "orc_solve_rule"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -186,7 +187,18 @@ def root_branches(rows) -> int:
 
 
 def tomita(rows) -> dict:
+    """Alg. 2 with the Tomita pivot on the input labels (no reordering)."""
     return _solve(_load().orc_tomita, rows)
+
+
+RULES = {"greedy": 0, "tomita_bb": 1, "greedy_tx": 2}
+
+
+def solve_rule(rows, rule: str) -> dict:
+    """Alg. 4 on the maximum-degree-first ordering with the pivot rule
+    "greedy" (GreedyBB), "tomita_bb" (TomitaBB) or "greedy_tx" (GreedyBBTX,
+    whose tree GreedyBBNX shares)."""
+    return _solve(_load().orc_solve_rule, rows, RULES[rule])
 
 
 def brute(rows) -> dict:
@@ -220,7 +232,7 @@ def subproblem(rows, R, P, X, mode: str = "greedy", ids=None) -> dict:
     (rows given in that numbering).  ids[label] is the id a clique member is
     reported (and hashed) as; None keeps the labels."""
     rows, n, rw = _rows(rows)
-    m = {"greedy": 0, "tomita": 1}[mode]
+    m = {"greedy": 0, "tomita": 1, "greedy_tx": 2}[mode]
     Ra = np.ascontiguousarray(list(R) or [0], dtype=np.uint32)
     Pa = np.ascontiguousarray(list(P) or [0], dtype=np.uint32)
     Xa = np.ascontiguousarray(list(X) or [0], dtype=np.uint32)

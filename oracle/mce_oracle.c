@@ -16,6 +16,11 @@
  *     maximum-degree-first ordering of Sec. 4.2 and the GreedyBB pivot rule of
  *     Sec. 4.3: orc_greedy.  This also fixes the node ("step") count, which
  *     depends on the search tree.
+ *   - The same search with the other pivot rules of Sec. 4.3 and Sec. 5:
+ *     GreedyBBTX (pivot from X maximising |P cap N(p)|, else the first of P;
+ *     GreedyBBNX finds the same pivot with Naude's early exit, so its tree is
+ *     the same) and TomitaBB (the Tomita pivot over P cup X, on the
+ *     maximum-degree-first ordering): orc_solve_rule.
  *
  * Readings taken where the paper is silent or garbled (each one is listed in
  * the design notes of the repository):
@@ -274,7 +279,7 @@ typedef struct {
     uint32_t *report_buf;  /* scratch for input ids of a reported clique */
     arena ar;
     sink *out;
-    int tomita;            /* 0: GreedyBB pivot, 1: Tomita pivot */
+    int tomita;            /* pivot rule: 0 GreedyBB, 1 Tomita, 2 GreedyBBTX */
 } search;
 
 static void report_R_plus(search *s, uint32_t v)
@@ -308,15 +313,19 @@ static void sorted_insert(uint32_t *a, uint32_t *na, uint32_t v)
  * the ordering if X is non-empty, else the first vertex of P.  P and X are
  * sorted by position, so "first" is element 0.
  * Tomita (Sec. 3.2): a vertex u of P cup X maximising |P cap N(u)|; ties go to
- * the smaller label. */
+ * the smaller label.
+ * GreedyBBTX (Sec. 4.3): if X is non-empty, a vertex u of X maximising
+ * |P cap N(u)| (ties to the smaller label, as for all rules of Sec. 4.3);
+ * else the first vertex of P. */
 static uint32_t choose_pivot(const search *s, const uint32_t *P, uint32_t np,
                              const uint32_t *X, uint32_t nx)
 {
-    if (!s->tomita) return nx ? X[0] : P[0];
+    if (s->tomita == 0) return nx ? X[0] : P[0];
+    if (s->tomita == 2 && nx == 0) return P[0];
     const graph *g = s->pg;
     uint32_t best = UINT32_MAX;
     uint32_t best_score = 0;
-    for (int side = 0; side < 2; side++) {
+    for (int side = (s->tomita == 2 ? 1 : 0); side < 2; side++) {
         const uint32_t *S = side ? X : P;
         uint32_t ns = side ? nx : np;
         for (uint32_t i = 0; i < ns; i++) {
@@ -547,6 +556,17 @@ int orc_greedy_range(uint32_t n, const uint64_t *rows, uint32_t row_words, uint6
     return solve_range(n, rows, row_words, 0, 0, first, last, &out);
 }
 
+/* The search of Alg. 4 on the maximum-degree-first ordering under a pivot
+ * rule: 0 GreedyBB (same as orc_greedy), 1 TomitaBB, 2 GreedyBBTX. */
+int orc_solve_rule(uint32_t n, const uint64_t *rows, uint32_t row_words, int rule, orc_result *res)
+{
+    if (!res || rule < 0 || rule > 2) return ORC_E_INVAL;
+    result_clear(res);
+    sink out;
+    sink_init(&out, res);
+    return solve_range(n, rows, row_words, rule, 0, 0, UINT64_MAX, &out);
+}
+
 /* Number of children of the GreedyBB root, |L0|. */
 int orc_root_branches(uint32_t n, const uint64_t *rows, uint32_t row_words, uint64_t *out)
 {
@@ -595,14 +615,14 @@ int orc_tomita(uint32_t n, const uint64_t *rows, uint32_t row_words, orc_result 
 /* One subproblem (R, P, X) of a graph whose labels are taken as the positions
  * of the ordering (no reordering).  R, P, X are lists of labels; P and X need
  * not be sorted.  The subproblem root is counted as a node when P is
- * non-empty.  mode 0: GreedyBB pivot, 1: Tomita pivot.  ids (may be NULL: the
+ * non-empty.  mode 0: GreedyBB pivot, 1: Tomita pivot, 2: GreedyBBTX pivot.  ids (may be NULL: the
  * labels themselves) gives the id reported for each label: cliques are mapped
  * through it and sorted before they are hashed. */
 int orc_subproblem(uint32_t n, const uint64_t *rows, uint32_t row_words, int mode, const uint32_t *ids,
                    const uint32_t *R, uint32_t nr, const uint32_t *P, uint32_t np,
                    const uint32_t *X, uint32_t nx, orc_result *res)
 {
-    if (!res || (mode != 0 && mode != 1)) return ORC_E_INVAL;
+    if (!res || mode < 0 || mode > 2) return ORC_E_INVAL;
     result_clear(res);
     graph g;
     int rc = graph_from_rows(&g, n, rows, row_words);

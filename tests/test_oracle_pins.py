@@ -11,7 +11,9 @@ What pins what:
     at most 6 vertices and on seeded G(n, p) up to 20 vertices;
   * the node count (the paper's "steps"): closed forms for complete, empty,
     Moon-Moser and equal-part multipartite graphs, the subproblem of the
-    worked example (Sec. 5) and the GreedyBB / TomitaBB columns of Table 1;
+    worked example (Sec. 5), a hand-worked node where the pivot rules of
+    Sec. 4.3 disagree, and the GreedyBB / GreedyBBNX / TomitaBB columns of
+    Table 1;
   * the ordering: hand cases where the degree taken in the remaining graph
     and the static degree give different orders (Sec. 4.2), and the argmax
     property on seeded graphs;
@@ -106,13 +108,16 @@ def test_complete(orc, n):
     # one node per level: the root, then a chain of n - 1 nodes
     assert r["nodes"] == n and r["children"] == n and r["dead_ends"] == 0
     assert orc.tomita(synth.complete(n))["nodes"] == n
+    for rule in ("tomita_bb", "greedy_tx"):
+        assert orc.solve_rule(synth.complete(n), rule)["nodes"] == n
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 64, 100])
 def test_empty(orc, n):
-    r = orc.greedy(synth.empty(n))
-    assert r["count"] == n and r["hist"][1] == n and r["omega"] == 1
-    assert r["nodes"] == 1 and r["children"] == n and r["dead_ends"] == 0
+    for rule in ("greedy", "tomita_bb", "greedy_tx"):
+        r = orc.solve_rule(synth.empty(n), rule)
+        assert r["count"] == n and r["hist"][1] == n and r["omega"] == 1
+        assert r["nodes"] == 1 and r["children"] == n and r["dead_ends"] == 0
 
 
 def test_zero_vertices(orc):
@@ -157,6 +162,10 @@ def test_complete_multipartite(orc, parts):
         # each node branches on every vertex of its first part; the tree is
         # full a-ary of depth k - 1 over the nodes
         assert r["nodes"] == (a ** k - 1) // (a - 1)
+        # every vertex has the same degree and X meets no candidate's
+        # neighbourhood, so all three rules pivot on the first vertex of P
+        for rule in ("tomita_bb", "greedy_tx"):
+            assert orc.solve_rule(rows, rule)["nodes"] == (a ** k - 1) // (a - 1)
     assert orc.tomita(rows)["count"] == prod
 
 
@@ -209,6 +218,8 @@ def test_all_small_graphs(orc, n):
         b = orc.brute(rows)
         _same_report(orc.greedy(rows), b)
         _same_report(orc.tomita(rows), b)
+        for rule in ("tomita_bb", "greedy_tx"):
+            _same_report(orc.solve_rule(rows, rule), b)
 
 
 def test_all_graphs_on_six_vertices(orc):
@@ -228,6 +239,12 @@ def test_seeded_gnp_vs_brute(orc, n, p):
         b = orc.brute(rows)
         _same_report(orc.greedy(rows), b)
         _same_report(orc.tomita(rows), b)
+        for rule in ("tomita_bb", "greedy_tx"):
+            r = orc.solve_rule(rows, rule)
+            _same_report(r, b)
+            # every child is a new node, a maximal clique or a dead end; the
+            # root is a node but no child
+            assert r["children"] == r["nodes"] - 1 + r["count"] + r["dead_ends"]
 
 
 @pytest.mark.parametrize("n,p", [(40, 0.5), (70, 0.3), (25, 0.8)])
@@ -426,3 +443,41 @@ def test_subproblem_partition(orc):
     tot["hash_sum"] &= M64
     for k in tot:
         assert tot[k] == full[k], k
+
+
+def test_pivot_rules_hand_worked_node(orc):
+    """A node where the rules of Sec. 4.3 disagree, worked by hand.  Vertices
+    0..4 (positions), edges 0-2, 1-2, 1-3, 1-4, 2-3; node R = {}, P = {2, 3, 4},
+    X = {0, 1}.
+      GreedyBB: pivot = first of X = 0, L = P minus N(0) = {3, 4}.  Child 3:
+        P' = {2}, X' = {1}: a node, whose pivot 1 (first of X') leaves
+        L = {2} minus N(1) empty.  Child 4: P' = {}, X' = {1}: a dead end.
+        Nodes 2 (this one and child 3), children 2, one dead end, no clique.
+      GreedyBBTX: pivot = the vertex of X with most neighbours in P: 1 (three)
+        beats 0 (one), so L = P minus N(1) is empty: one node, no child.
+      Tomita: over P u X the scores are 0:1, 1:3, 2:1, 3:1, 4:0, so again 1."""
+    rows = _adj_from_edges(5, [(0, 2), (1, 2), (1, 3), (1, 4), (2, 3)])
+    g = orc.subproblem(rows, [], [2, 3, 4], [0, 1], mode="greedy")
+    assert (g["nodes"], g["children"], g["dead_ends"], g["count"]) == (2, 2, 1, 0)
+    for mode in ("greedy_tx", "tomita"):
+        t = orc.subproblem(rows, [], [2, 3, 4], [0, 1], mode=mode)
+        assert (t["nodes"], t["children"], t["dead_ends"], t["count"]) == (1, 0, 0, 0), mode
+
+
+def test_table1_step_calibration_other_rules(orc):
+    """Nodes per maximal clique of TomitaBB (Tomita pivot on the
+    maximum-degree-first ordering) and GreedyBBTX (the tree of GreedyBBNX)
+    over 5 seeds vs the TomitaBB and GreedyBBNX steps per clique of Table 1."""
+    with open(os.path.join(GOLDEN, "table1_random.json")) as f:
+        rows = json.load(f)["rows"]
+    for r in rows:
+        if r["mu"] > 1e6:
+            continue
+        res = {rule: [orc.solve_rule(synth.gnp(r["n"], r["p"], s), rule) for s in range(5)]
+               for rule in ("tomita_bb", "greedy_tx")}
+        mu = np.mean([x["count"] for x in res["tomita_bb"]])
+        tb = np.mean([x["nodes"] for x in res["tomita_bb"]]) / mu
+        nx = np.mean([x["nodes"] for x in res["greedy_tx"]]) / mu
+        # measured: within 2% on every row (seeds 0-4)
+        assert abs(tb / (r["tomitabb_steps"] / r["mu"]) - 1.0) < 0.04, (r, tb)
+        assert abs(nx / (r["greedybbnx_steps"] / r["mu"]) - 1.0) < 0.04, (r, nx)
