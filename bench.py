@@ -179,6 +179,27 @@ def serving(mce, synth, np, count: int, warm: int) -> dict:
     return result
 
 
+def pivot_rules(mce, d_rows, reps: int) -> dict:
+    """The workload graph under each pivot rule of Sec. 4.3 (automatic
+    schedule): the same cliques, different trees; solve time of one handle."""
+    out = {}
+    for rule in ("greedy", "greedy_tx", "tomita_bb"):
+        mce.reset_options(watchdog_ms=120000, pivot=mce.PIVOT_RULES[rule])
+        g = mce.Graph(d_rows)
+        g.count()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = g.count()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        g.release()
+        out[rule] = {"solve_ms": best * 1e3, "nodes": r["nodes"], "children": r["children"],
+                     "cliques_per_s": r["count"] / best, "nodes_per_s": r["nodes"] / best}
+    mce.reset_options(watchdog_ms=120000)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +211,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-rules", action="store_true", help="skip the pivot-rule comparison")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="automatic schedule instead of mce_autotune's")
     ap.add_argument("--opts", default="", metavar="K=V,...",
@@ -300,6 +322,8 @@ def main():
                      "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"]},
     }
     mce.reset_options(watchdog_ms=120000)
+    if not args.no_rules:
+        line["pivot_rules"] = pivot_rules(mce, d_rows, reps=3)
     if not args.no_batch:
         line["batched"] = batched(mce, synth, np, reps=3, tune=not args.no_tune)
     if not args.no_serving:

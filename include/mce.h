@@ -74,6 +74,15 @@ extern "C" {
 #define MCE_OPT_REFRESH_CHILDREN 9 /* children a busy workgroup processes between two looks
                                       at its mailbox for workgroups asking for work (0 = auto:
                                       the check interval, i.e. at every check) */
+#define MCE_OPT_PIVOT 10           /* pivot rule of the search (Sec. 4.3; the maximal cliques
+                                      are the same under every rule, the tree and its node
+                                      count are not):
+                                        0 GreedyBB (default): the first vertex of X in the
+                                          ordering, else the first of P;
+                                        1 TomitaBB: a vertex of P u X maximising |P n N(p)|;
+                                        2 GreedyBBTX: a vertex of X maximising |P n N(p)|, else
+                                          the first of P (GreedyBBNX picks the same pivot).
+                                      Ties go to the earlier vertex of the ordering. */
 
 typedef struct mce_graph_s *mce_graph_t; /* opaque; owns the device copy, order and rows */
 

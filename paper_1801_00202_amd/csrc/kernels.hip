@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(64) root_units_kernel(SearchParams sp, uint64_
 
 // One node (R, P, X) of graph 0, given as position bitsets (w32 words each,
 // R then P then X), as the only unit of the pool: R is mapped to input ids,
-// the node's pivot (first of X, else first of P) and L = P \ N(p) are taken
+// the node's pivot (by the launch's pivot rule) and L = P \ N(p) are taken
 // as in Alg. 4, and the node itself is counted.  One wavefront.  P must not be
 // empty (the host checks).
 template <int WPL>
@@ -545,6 +545,29 @@ __global__ void __launch_bounds__(64) subproblem_kernel(SearchParams sp, const u
         set_bit<WPL>(Rb, bcast0(ord[q]), lane);
     }
     int p = first_bit<WPL>(X);
+    if (sp.pivot_rule == kPivotTomita || (sp.pivot_rule == kPivotTX && p >= 0)) {
+        // the candidate maximising |P n N(u)|, the earliest on ties
+        uint32_t C[WPL];
+#pragma unroll
+        for (int c = 0; c < WPL; c++) C[c] = (sp.pivot_rule == kPivotTomita) ? (P[c] | X[c]) : X[c];
+        uint32_t bestc = 0;
+        p = -1;
+        for (int u = first_bit<WPL>(C); u >= 0; u = first_bit<WPL>(C)) {
+            clear_bit<WPL>(C, (uint32_t)u, lane);
+            const uint32_t* ru = adj + (size_t)(uint32_t)u * gd.rstride;
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t w = (uint32_t)c * 64u + lane;
+                cnt += (w < W) ? (uint32_t)__builtin_popcount(P[c] & ru[w]) : 0u;
+            }
+            cnt = wave_sum(cnt);
+            if (p < 0 || cnt > bestc) {
+                p = u;
+                bestc = cnt;
+            }
+        }
+    }
     if (p < 0) p = first_bit<WPL>(P);
     if (p < 0) return;
     const uint32_t* rp = adj + (size_t)(uint32_t)p * gd.rstride;
@@ -1043,7 +1066,7 @@ constexpr uint32_t kUnitDone = 0, kUnitAbort = 1, kUnitCheck = 2, kUnitFlush = 3
 // with resume = 1.  Counters since the last return are added to the
 // wavefront's totals before every return.  wl_off: word offset of the
 // wavefront's LDS block.
-template <int WPL>
+template <int WPL, int RULE>
 __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __restrict__ spp_v, uint32_t wl_off,
                                                           LaneBits<WPL> Rbb, LaneBits<WPL> Pb, LaneBits<WPL> Xb,
                                                           LaneBits<WPL> Lb, uint32_t g_v, uint32_t resume_v)
@@ -1270,16 +1293,62 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
                 P[c] = P2[c];
                 X[c] = X2[c];
             }
-            // step 9: pivot = first of X if X is non-empty, else first of P.
-            // The row of the first of P is requested with the pivot's: it is
-            // the first candidate whenever it is not adjacent to the pivot
-            // (always when the pivot is that vertex).
+            // step 9: the pivot.  GreedyBB: the first of X if X is non-empty,
+            // else the first of P.  The row of the first of P is requested
+            // with the pivot's: it is the first candidate whenever it is not
+            // adjacent to the pivot (always when the pivot is that vertex).
             const int px = first_pos<WPL>(X, lane_lo);
             const int pp = first_pos<WPL>(P, lane_lo);
-            const uint32_t piv = px >= 0 ? (uint32_t)px : (uint32_t)pp;
             uint32_t prow[WPL], frow[WPL];
-            load_row(piv, prow);
-            load_row((uint32_t)pp, frow);
+            if (RULE == (int)kPivotGreedy || (RULE == (int)kPivotTX && px < 0)) {
+                const uint32_t piv = px >= 0 ? (uint32_t)px : (uint32_t)pp;
+                load_row(piv, prow);
+                load_row((uint32_t)pp, frow);
+            } else {
+                // TomitaBB (candidates P u X) and GreedyBBTX (candidates X):
+                // the candidate u maximising |P n N(u)|, the earliest on ties.
+                // Candidates are taken in order, the next one's row on its way
+                // while the current one is counted; no candidate can beat
+                // |P| (only a vertex of X reaches it), so the scan stops there.
+                load_row((uint32_t)pp, frow);
+                uint32_t C[WPL];
+                uint32_t pc = 0;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    C[c] = (RULE == (int)kPivotTomita) ? (P[c] | X[c]) : X[c];
+                    pc += (uint32_t)__builtin_popcount(P[c]);
+                }
+                const uint32_t psize = wave_sum(pc);
+                int u = first_pos<WPL>(C, lane_lo);
+                uint32_t urow[WPL];
+                load_row((uint32_t)u, urow);
+                uint32_t bestc = 0;
+                bool have = false;
+                for (;;) {
+                    uint32_t mu[WPL];
+                    bit_mask<WPL>((uint32_t)u, lane_lo, mu);
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) C[c] &= ~mu[c];
+                    const int nu = first_pos<WPL>(C, lane_lo);
+                    uint32_t urow2[WPL];
+                    load_row(nu >= 0 ? (uint32_t)nu : (uint32_t)u, urow2);
+                    uint32_t cnt = 0;
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) cnt += (uint32_t)__builtin_popcount(P[c] & urow[c]);
+                    cnt = wave_sum(cnt);
+                    if (!have || cnt > bestc) {
+                        have = true;
+                        bestc = cnt;
+#pragma unroll
+                        for (int c = 0; c < WPL; c++) prow[c] = urow[c];
+                        if (cnt == psize) break;
+                    }
+                    if (nu < 0) break;
+                    u = nu;
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) urow[c] = urow2[c];
+                }
+            }
             // step 10: L = P \ N(p)
 #pragma unroll
             for (int c = 0; c < WPL; c++) L[c] = P[c] & ~prow[c];
@@ -1380,7 +1449,7 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
     return why;
 }
 
-template <int WPL>
+template <int WPL, int RULE>
 __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const SearchParams* __restrict__ spp)
 {
     // sp (by value) serves the hot path, where its pointers are known to be
@@ -1674,7 +1743,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
         const uint32_t W = bcast0(sp.graphs[g].w32);
         bool abort = false;
         for (uint32_t resume = 0;; resume = 1) {
-            const uint32_t why = bcast0(search_unit<WPL>(spp, wl_off, ub[0], ub[1], ub[2], ub[3], g, resume));
+            const uint32_t why = bcast0(search_unit<WPL, RULE>(spp, wl_off, ub[0], ub[1], ub[2], ub[3], g, resume));
             if (why == kUnitDone) break;
             if (why == kUnitCheck) {
                 if (lane == 0) ctx->checks += 1;
@@ -1840,6 +1909,19 @@ hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uin
     return hipGetLastError();
 }
 
+typedef void (*SearchFn)(SearchParams, const SearchParams*);
+
+// The search kernel for a bitset width (chunks per lane) and a pivot rule.
+static SearchFn search_fn(uint32_t max_w32, uint32_t rule)
+{
+    const bool one = search_chunks(max_w32) == 1;
+    switch (rule) {
+    case kPivotTomita: return one ? search_kernel<1, kPivotTomita> : search_kernel<2, kPivotTomita>;
+    case kPivotTX: return one ? search_kernel<1, kPivotTX> : search_kernel<2, kPivotTX>;
+    default: return one ? search_kernel<1, kPivotGreedy> : search_kernel<2, kPivotGreedy>;
+    }
+}
+
 static hipError_t ensure_search_attr()
 {
     // Allow the search kernels the full LDS of a workgroup once per process.
@@ -1849,10 +1931,11 @@ static hipError_t ensure_search_attr()
         int dev = 0, lds = 0;
         err = hipGetDevice(&dev);
         if (err == hipSuccess) err = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (err == hipSuccess)
-            err = hipFuncSetAttribute((const void*)search_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (err == hipSuccess)
-            err = hipFuncSetAttribute((const void*)search_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        for (uint32_t w32 : {1u, 2u * kOneChunkMaxW32})
+            for (uint32_t rule : {kPivotGreedy, kPivotTomita, kPivotTX})
+                if (err == hipSuccess)
+                    err = hipFuncSetAttribute((const void*)search_fn(w32, rule),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     });
     return err;
 }
@@ -1864,17 +1947,15 @@ hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint3
     const uint32_t lds = search_lds_bytes(sp.wave_lds_words, sp.rec_words, waves_per_block);
     hipError_t e = ensure_search_attr();
     if (e != hipSuccess) return e;
-    if (search_chunks(max_w32) == 1)
-        hipLaunchKernelGGL(search_kernel<1>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp, d_sp);
-    else
-        hipLaunchKernelGGL(search_kernel<2>, dim3(blocks), dim3(64 * waves_per_block), lds, s, sp, d_sp);
+    hipLaunchKernelGGL(search_fn(max_w32, sp.pivot_rule), dim3(blocks), dim3(64 * waves_per_block), lds, s, sp,
+                       d_sp);
     return hipGetLastError();
 }
 
-hipError_t search_occupancy(uint32_t max_w32, uint32_t waves_per_block, uint32_t lds_bytes,
+hipError_t search_occupancy(uint32_t max_w32, uint32_t rule, uint32_t waves_per_block, uint32_t lds_bytes,
                             int* blocks_per_cu)
 {
-    const void* k = search_chunks(max_w32) == 1 ? (const void*)search_kernel<1> : (const void*)search_kernel<2>;
+    const void* k = (const void*)search_fn(max_w32, rule);
     hipError_t e = ensure_search_attr();
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, (int)(64 * waves_per_block),

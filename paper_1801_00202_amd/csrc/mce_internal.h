@@ -132,7 +132,11 @@ struct SearchParams {
     uint32_t refresh_children; // children a workgroup processes between two looks at its mailbox
     uint32_t poll_iters;       // idle iterations between two looks at the end-of-search counter
     uint32_t* wave_state;     // per wavefront: kWave* phase (for deadline reports), or null
+    uint32_t pivot_rule;      // kPivot*
 };
+// Pivot rules (SearchParams.pivot_rule, MCE_OPT_PIVOT).
+constexpr uint32_t kPivotGreedy = 0, kPivotTomita = 1, kPivotTX = 2;
+
 // Phases recorded in SearchParams.wave_state.
 constexpr uint32_t kWaveIdle = 1, kWaveFetch = 2, kWaveBusy = 3, kWaveExited = 4;
 
@@ -157,7 +161,7 @@ hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max
 hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uint32_t* bits, hipStream_t s);
 hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s);
-hipError_t search_occupancy(uint32_t max_w32, uint32_t waves_per_block, uint32_t lds_bytes,
+hipError_t search_occupancy(uint32_t max_w32, uint32_t rule, uint32_t waves_per_block, uint32_t lds_bytes,
                             int* blocks_per_cu);
 
 } // namespace mce

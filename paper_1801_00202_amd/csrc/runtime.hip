@@ -37,6 +37,7 @@ struct Options {
     int64_t watchdog_ms = 0;     // 0: none
     int64_t graph = 1;           // hipGraph replay: 0 never, 1 batches, 2 always
     int64_t refresh_children = 0; // 0: auto
+    int64_t pivot = 0;            // kPivot*
 };
 
 std::mutex g_opt_mu;
@@ -274,9 +275,10 @@ struct LaunchCfg {
     uint32_t w32cap = 0;
     uint32_t spill_levels = 0;
     uint32_t spill_chunks = 0;
+    uint32_t rule = 0; // pivot rule (kPivot*)
     bool operator==(const LaunchCfg& o) const
     {
-        return wpb == o.wpb && blocks == o.blocks && lds_depth == o.lds_depth &&
+        return rule == o.rule && wpb == o.wpb && blocks == o.blocks && lds_depth == o.lds_depth &&
                split_threshold == o.split_threshold && check_interval == o.check_interval &&
                cap == o.cap && wave_lds_words == o.wave_lds_words && slot_words == o.slot_words &&
                w32cap == o.w32cap && spill_levels == o.spill_levels && spill_chunks == o.spill_chunks;
@@ -346,6 +348,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16)
                                   : (h->tune.wpb ? h->tune.wpb : 8u);
     c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
+    c.rule = (uint32_t)o.pivot;
     c.slot_words = lds_frame_words(c.w32cap);
     const uint32_t slack = lds_slack_words(c.w32cap);
     const uint32_t rec_words = kRecHeader + 4 * c.w32cap;
@@ -361,7 +364,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         // workgroups that the registers allow on a CU also fit in its LDS;
         // frames below it go to the spill pool.
         int by_regs = 0;
-        HIP_TRY(search_occupancy(h->max_w32, c.wpb, 0, &by_regs));
+        HIP_TRY(search_occupancy(h->max_w32, c.rule, c.wpb, 0, &by_regs));
         uint32_t wgs = (uint32_t)std::max(by_regs, 1);
         if (o.blocks <= 0 && h->tune.wgs_per_cu) wgs = std::min(wgs, h->tune.wgs_per_cu);
         depth = kAutoDepth;
@@ -385,7 +388,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         c.blocks = (uint32_t)o.blocks;
     } else {
         int bpc = 0;
-        HIP_TRY(search_occupancy(h->max_w32, c.wpb, lds_bytes, &bpc));
+        HIP_TRY(search_occupancy(h->max_w32, c.rule, c.wpb, lds_bytes, &bpc));
         if (bpc < 1) bpc = 1;
         if (h->tune.wgs_per_cu) bpc = std::min<int>(bpc, (int)h->tune.wgs_per_cu);
         c.blocks = (uint32_t)di.cus * (uint32_t)bpc;
@@ -453,6 +456,7 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
     sp.wave_lds_words = c.wave_lds_words;
     sp.split_threshold = c.split_threshold;
     sp.check_interval = c.check_interval;
+    sp.pivot_rule = c.rule;
     const Options o = options();
     DeviceInfo di;
     const bool have_clock = device_info(&di) == MCE_OK && di.wall_khz > 0;
@@ -731,6 +735,10 @@ int mce_set_option(int key, int64_t value)
         if (value < 0 || value > (1 << 30)) return MCE_E_INVAL;
         g_opt.refresh_children = value;
         return MCE_OK;
+    case MCE_OPT_PIVOT:
+        if (value < 0 || value > 2) return MCE_E_INVAL;
+        g_opt.pivot = value;
+        return MCE_OK;
     default: return MCE_E_INVAL;
     }
 }
@@ -749,6 +757,7 @@ int mce_get_option(int key, int64_t* value)
     case MCE_OPT_WATCHDOG_MS: *value = g_opt.watchdog_ms; return MCE_OK;
     case MCE_OPT_GRAPH: *value = g_opt.graph; return MCE_OK;
     case MCE_OPT_REFRESH_CHILDREN: *value = g_opt.refresh_children; return MCE_OK;
+    case MCE_OPT_PIVOT: *value = g_opt.pivot; return MCE_OK;
     default: return MCE_E_INVAL;
     }
 }
@@ -1071,7 +1080,7 @@ int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t* out, void* hip_
     const mce_graph_s::Tune shape0 = best_t;
     for (uint32_t wpb : {4u, 8u, 16u}) {
         int by_regs = 0;
-        HIP_TRY(search_occupancy(g->max_w32, wpb, 0, &by_regs));
+        HIP_TRY(search_occupancy(g->max_w32, (uint32_t)options().pivot, wpb, 0, &by_regs));
         for (uint32_t k = 1; k <= (uint32_t)std::min(by_regs, 4); k++) {
             if (wpb == shape0.wpb && k == shape0.wgs_per_cu) continue;
             mce_graph_s::Tune t = shape0;
@@ -1264,7 +1273,7 @@ int server_start()
     sv.device = di.device;
     sv.hbm_budget = free_b / 2;
     int bpc = 0;
-    HIP_TRY(search_occupancy(64, 4, (kWaveFixedWords + 16 * 193) * 16, &bpc));
+    HIP_TRY(search_occupancy(64, kPivotGreedy, 4, (kWaveFixedWords + 16 * 193) * 16, &bpc));
     sv.blocks_total = (uint32_t)di.cus * (uint32_t)std::max(bpc, 1);
     for (uint32_t i = 0; i < kSlots; i++) sv.workers.emplace_back(worker_loop, i);
     sv.started = true;

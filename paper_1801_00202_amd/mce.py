@@ -38,11 +38,15 @@ OPTIONS = {
     "watchdog_ms": 7,
     "graph": 8,
     "refresh_children": 9,
+    "pivot": 10,
 }
 DEFAULTS = {
     "waves_per_block": 0, "blocks": 0, "lds_depth": -1, "split_threshold": 0,
     "check_interval": 0, "queue_cap": 0, "watchdog_ms": 0, "graph": 1, "refresh_children": 0,
+    "pivot": 0,
 }
+# values of the "pivot" option (MCE_OPT_PIVOT)
+PIVOT_RULES = {"greedy": 0, "tomita_bb": 1, "greedy_tx": 2}
 
 
 class MceError(RuntimeError):

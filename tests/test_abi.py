@@ -155,8 +155,9 @@ def test_options(lib, mce):
         assert lib.mce_set_option(mce.OPTIONS["queue_cap"], 1000) == mce.E_INVAL    # not a power of two
         assert lib.mce_set_option(mce.OPTIONS["lds_depth"], -2) == mce.E_INVAL
         assert lib.mce_set_option(mce.OPTIONS["graph"], 3) == mce.E_INVAL
+        assert lib.mce_set_option(mce.OPTIONS["pivot"], 3) == mce.E_INVAL
         for name, key in mce.OPTIONS.items():
-            val = 2 if name == "graph" else 4
+            val = 2 if name in ("graph", "pivot") else 4
             assert lib.mce_set_option(key, val) == mce.OK
             assert lib.mce_get_option(key, ctypes.byref(v)) == mce.OK and v.value == val
     finally:

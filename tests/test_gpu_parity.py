@@ -224,3 +224,61 @@ def test_autotune_keeps_results(mce, orc, n, p, seed):
         same(g.count(), ref)
     finally:
         g.release()
+
+
+# ------------------------------------------------ pivot rules (Sec. 4.3) ---
+
+RULES = ("tomita_bb", "greedy_tx")
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("n,p,seed", [(100, 0.5, 0), (100, 0.6, 1), (33, 0.6, 3), (64, 0.9, 4), (129, 0.6, 8),
+                                      (300, 0.3, 10), (513, 0.2, 11), (700, 0.1, 12), (2100, 0.03, 5)])
+def test_pivot_rules(mce, orc, rule, n, p, seed):
+    """TomitaBB and GreedyBBTX on the GPU: the oracle's counters exactly
+    (the tree, hence nodes, children and dead ends, depends on the rule)."""
+    rows = synth.gnp(n, p, seed)
+    mce.set_option("pivot", mce.PIVOT_RULES[rule])
+    res, g = solve(mce, rows)
+    same(res, orc.solve_rule(rows, rule))
+    g.release()
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_pivot_rules_batch(mce, orc, rule):
+    graphs = [synth.gnp(n, p, 40 + i) for i, (n, p) in enumerate([(50, 0.5), (90, 0.4), (30, 0.8), (140, 0.2),
+                                                                   (64, 0.6), (1, 0.5), (0, 0.5), (200, 0.1)])]
+    mce.set_option("pivot", mce.PIVOT_RULES[rule])
+    b = mce.Graph(batch=graphs)
+    try:
+        out = b.count()
+        for r, rows in zip(out, graphs):
+            same(r, orc.solve_rule(rows, rule))
+    finally:
+        b.release()
+
+
+@pytest.mark.parametrize("rule,mode", [("tomita_bb", "tomita"), ("greedy_tx", "greedy_tx")])
+def test_pivot_rules_subproblem(mce, orc, rule, mode):
+    """mce_count_subproblem picks the node's own pivot by the rule too."""
+    rows = synth.gnp(160, 0.5, 6)
+    order = orc.order(rows)
+    adj = synth.unpack_rows(rows)
+    pos = adj[np.ix_(order, order)]
+    rows_pos = synth.pack_rows(pos)
+    rng = np.random.Generator(np.random.PCG64(9))
+    mce.set_option("pivot", mce.PIVOT_RULES[rule])
+    g = mce.Graph(rows)
+    try:
+        for _ in range(4):
+            v = int(rng.integers(0, 160))
+            C = [u for u in range(160) if pos[v, u]]
+            xm = rng.random(len(C)) < 0.3
+            P = [u for u, m in zip(C, xm) if not m]
+            X = [u for u, m in zip(C, xm) if m]
+            if not P:
+                continue
+            ref = orc.subproblem(rows_pos, [v], P, X, mode=mode, ids=order)
+            same(g.count_subproblem([v], P, X), ref)
+    finally:
+        g.release()
