@@ -200,6 +200,26 @@ def pivot_rules(mce, d_rows, reps: int) -> dict:
     return out
 
 
+def streamed_enumerate(mce, d_rows) -> dict:
+    """Every clique of the workload graph as sorted input ids, streamed to
+    the host in chunks of 2^24 ids (mce_enumerate_stream, automatic
+    schedule); the sink only counts what arrives."""
+    g = mce.Graph(d_rows)
+    got = [0, 0]
+
+    def on_chunk(verts, pairs):
+        got[0] += len(pairs)
+        got[1] += len(verts)
+
+    t0 = time.perf_counter()
+    r = g.enumerate_stream(on_chunk)
+    dt = time.perf_counter() - t0
+    g.release()
+    assert got[0] == r["count"]
+    return {"seconds": dt, "cliques_per_s": r["count"] / dt, "ids": got[1],
+            "host_bytes_per_s": (4 * got[1] + 16 * got[0]) / dt}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +232,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rules", action="store_true", help="skip the pivot-rule comparison")
+    ap.add_argument("--no-enumerate", action="store_true", help="skip the streamed enumeration")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="automatic schedule instead of mce_autotune's")
     ap.add_argument("--opts", default="", metavar="K=V,...",
@@ -324,6 +345,8 @@ def main():
     mce.reset_options(watchdog_ms=120000)
     if not args.no_rules:
         line["pivot_rules"] = pivot_rules(mce, d_rows, reps=3)
+    if not args.no_enumerate:
+        line["enumerate_stream"] = streamed_enumerate(mce, d_rows)
     if not args.no_batch:
         line["batched"] = batched(mce, synth, np, reps=3, tune=not args.no_tune)
     if not args.no_serving:

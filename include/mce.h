@@ -192,6 +192,33 @@ int mce_enumerate(mce_graph_t g, uint32_t *verts, uint64_t verts_cap, uint64_t *
                   mce_result_t *res, void *hip_stream);
 
 /*
+ * mce_enumerate_stream -- single-graph handles only: every maximal clique as
+ * its sorted input ids, delivered in chunks to a caller function, with device
+ * and host memory bounded by the chunk size instead of the whole output.
+ *
+ * The root's children partition the search (each maximal clique lies in
+ * exactly one child's subtree, Alg. 4), so the library enumerates ranges of
+ * root children one after the other into a device buffer of chunk_verts ids
+ * (offsets: 2 * chunk_verts), copies each range's output to pinned host
+ * memory and calls
+ *     sink(user, verts, offsets, ncliques)
+ * where clique j of the chunk is verts[offsets[2j] .. offsets[2j+1]) (offsets
+ * relative to this chunk's verts; host pointers valid only during the call).
+ * Ranges grow and shrink with the output they produce; a range that overflows
+ * the chunk is enumerated again in smaller pieces, and a single child whose
+ * output alone exceeds the chunk gets a buffer of the size it needs.  The
+ * order of cliques is unspecified.  A sink returning non-zero stops the
+ * enumeration: MCE_E_CANCELLED, res then covers the ranges delivered so far.
+ *   chunk_verts  ids per chunk (0: 1 << 24)
+ *   res          totals of the whole graph (as mce_count; hist if given)
+ * Errors as mce_count; MCE_E_INVAL for a batch handle or a NULL sink/res.
+ */
+typedef int (*mce_clique_sink_t)(void *user, const uint32_t *verts, const uint64_t *offsets,
+                                 uint64_t ncliques);
+int mce_enumerate_stream(mce_graph_t g, uint64_t chunk_verts, mce_clique_sink_t sink, void *user,
+                         mce_result_t *res, void *hip_stream);
+
+/*
  * Serving.  mce_submit queues a count job for a prepared single-graph handle
  * and returns at once with a ticket.  Jobs run concurrently on the device as
  * capacity (HBM footprint and in-flight job slots) allows; a job that does not

@@ -301,6 +301,9 @@ struct mce_graph_s {
     DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params, d_sub;
     HostPinned h_params; // staging of the search parameters (stable for graph replays)
     HostPinned h_out; // results | ctl | hist, copied back in one go
+    // chunk buffers of mce_enumerate_stream
+    DevBuf d_sv, d_so;
+    HostPinned h_sv, h_so;
     // launch choices fixed for this handle by mce_autotune (0: automatic)
     struct Tune {
         uint32_t wpb = 0, wgs_per_cu = 0, split_threshold = 0, check_interval = 0;
@@ -1008,6 +1011,101 @@ int mce_enumerate(mce_graph_t g, uint32_t* verts, uint64_t verts_cap, uint64_t* 
         res->status = MCE_E_TRUNCATED;
         return MCE_E_TRUNCATED;
     }
+    return MCE_OK;
+}
+
+int mce_enumerate_stream(mce_graph_t g, uint64_t chunk_verts, mce_clique_sink_t sink, void* user,
+                         mce_result_t* res, void* hip_stream)
+{
+    if (!g || !res || !sink || g->num_graphs != 1) return MCE_E_INVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = finish_prepare_timing_locked(g);
+    if (rc != MCE_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const GraphDesc& gd = g->desc[0];
+    uint64_t* user_hist = res->hist;
+    const uint32_t user_len = res->hist_len;
+    if (gd.n == 0) {
+        fill_empty_graph(0, UINT64_MAX, res);
+        const uint64_t z[2] = {0, 0};
+        const uint32_t none = 0;
+        return sink(user, &none, z, 1) ? MCE_E_CANCELLED : MCE_OK;
+    }
+    if (chunk_verts == 0) chunk_verts = 1ull << 24;
+    // children of the root: position 0 and its non-neighbours
+    std::vector<uint32_t> row0(gd.w32);
+    HIP_TRY(hipMemcpy(row0.data(), g->d_adj.as<uint32_t>() + gd.adj_off, 4ull * gd.w32, hipMemcpyDeviceToHost));
+    uint64_t nb = 0;
+    for (uint32_t w = 0; w < gd.w32; w++) nb += (uint32_t)__builtin_popcount(row0[w]);
+    const uint64_t total = gd.n - nb;
+    // running totals
+    mce_result_t acc;
+    std::memset(&acc, 0, sizeof(acc));
+    std::vector<uint64_t> hist_acc(gd.n + 1, 0), hist_r(gd.n + 1, 0);
+    uint64_t cap_v = chunk_verts, cap_o = 2 * chunk_verts;
+    uint64_t a = 0, span = total; // the first try covers everything
+    while (a < total) {
+        if (span > total - a) span = total - a;
+        if ((rc = g->d_sv.ensure(4 * cap_v)) != MCE_OK) return rc;
+        if ((rc = g->d_so.ensure(8 * cap_o)) != MCE_OK) return rc;
+        mce_result_t r;
+        std::memset(&r, 0, sizeof(r));
+        r.hist = hist_r.data();
+        r.hist_len = (uint32_t)hist_r.size();
+        QueueCtl ctl;
+        rc = run_solve(g, a, a + span, &r, s, g->d_sv.as<uint32_t>(), cap_v, g->d_so.as<uint64_t>(), cap_o, &ctl,
+                       false);
+        if (rc != MCE_OK) return rc;
+        if (ctl.vcursor > cap_v || ctl.ocursor > cap_o) {
+            // too much output for the chunk: split the range, or (one child)
+            // give it the buffer it needs
+            if (span > 1) {
+                const double f = std::min((double)cap_v / (double)std::max<uint64_t>(ctl.vcursor, 1),
+                                          (double)cap_o / (double)std::max<uint64_t>(ctl.ocursor, 1));
+                span = std::max<uint64_t>(1, std::min<uint64_t>(span / 2, (uint64_t)((double)span * f * 0.8)));
+            } else {
+                cap_v = std::max<uint64_t>(cap_v, ctl.vcursor);
+                cap_o = std::max<uint64_t>(cap_o, ctl.ocursor);
+            }
+            continue;
+        }
+        // deliver the chunk
+        if ((rc = g->h_sv.ensure(4 * std::max<uint64_t>(ctl.vcursor, 1))) != MCE_OK) return rc;
+        if ((rc = g->h_so.ensure(8 * std::max<uint64_t>(ctl.ocursor, 1))) != MCE_OK) return rc;
+        if (ctl.vcursor)
+            HIP_TRY(hipMemcpyAsync(g->h_sv.p, g->d_sv.p, 4 * ctl.vcursor, hipMemcpyDeviceToHost, s));
+        if (ctl.ocursor)
+            HIP_TRY(hipMemcpyAsync(g->h_so.p, g->d_so.p, 8 * ctl.ocursor, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        acc.count += r.count;
+        acc.nodes += r.nodes;
+        acc.children += r.children;
+        acc.dead_ends += r.dead_ends;
+        acc.hash_xor ^= r.hash_xor;
+        acc.hash_sum += r.hash_sum;
+        acc.omega = std::max(acc.omega, r.omega);
+        for (size_t k = 0; k < hist_r.size(); k++) hist_acc[k] += hist_r[k];
+        a += span;
+        const bool stop = r.count && sink(user, static_cast<const uint32_t*>(g->h_sv.p),
+                                          static_cast<const uint64_t*>(g->h_so.p), r.count) != 0;
+        if (stop || a >= total) {
+            *res = acc;
+            res->hist = user_hist;
+            res->hist_len = user_len;
+            res->status = stop ? MCE_E_CANCELLED : MCE_OK;
+            if (user_hist)
+                for (uint32_t k = 0; k < user_len; k++) user_hist[k] = k < hist_acc.size() ? hist_acc[k] : 0;
+            return stop ? MCE_E_CANCELLED : MCE_OK;
+        }
+        // a range that used little of the chunk doubles for the next one
+        if (ctl.vcursor < cap_v / 4 && ctl.ocursor < cap_o / 4) span *= 2;
+    }
+    *res = acc;
+    res->hist = user_hist;
+    res->hist_len = user_len;
+    res->status = MCE_OK;
+    if (user_hist)
+        for (uint32_t k = 0; k < user_len; k++) user_hist[k] = k < hist_acc.size() ? hist_acc[k] : 0;
     return MCE_OK;
 }
 

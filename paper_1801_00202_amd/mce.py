@@ -119,7 +119,12 @@ EXPORTS = (
     "mce_prepare", "mce_num_graphs", "mce_get_order", "mce_root_branches", "mce_count",
     "mce_count_range", "mce_count_subproblem", "mce_enumerate", "mce_submit", "mce_poll", "mce_cancel", "mce_release",
     "mce_strerror", "mce_set_option", "mce_get_option", "mce_last_stats", "mce_autotune", "mce_clear_tuning",
+    "mce_enumerate_stream",
 )
+
+# mce_clique_sink_t
+SINK = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64)
 
 _LIB = None
 
@@ -161,6 +166,7 @@ def _lib():
         lib.mce_last_stats.argtypes = [ctypes.POINTER(Stats)]
         lib.mce_autotune.argtypes = [vp, u32, ctypes.POINTER(Tune), vp]
         lib.mce_clear_tuning.argtypes = [vp]
+        lib.mce_enumerate_stream.argtypes = [vp, u64, SINK, vp, pres, vp]
         for name in EXPORTS:
             if name != "mce_strerror":
                 getattr(lib, name).restype = i32
@@ -346,6 +352,34 @@ class Graph:
             raise MceError(rc, "mce_enumerate")
         res["truncated"] = rc == E_TRUNCATED
         return res, verts, offsets
+
+    def enumerate_stream(self, on_chunk, chunk_verts: int = 0, stream=None) -> dict:
+        """mce_enumerate_stream: on_chunk(verts, pairs) is called per chunk
+        with numpy copies (pairs[j] = (begin, end) of clique j in verts);
+        a true return value stops the enumeration.  Returns the totals, with
+        "cancelled" set when on_chunk stopped it."""
+        failure = []
+
+        def _sink(_user, v, o, count):
+            try:
+                pairs = np.ctypeslib.as_array(o, shape=(2 * int(count),)).reshape(-1, 2).copy()
+                nv = int(pairs[:, 1].max()) if count else 0
+                verts = np.ctypeslib.as_array(v, shape=(max(nv, 1),))[:nv].copy()
+                return 1 if on_chunk(verts, pairs) else 0
+            except BaseException as e:  # stop the library, re-raise below
+                failure.append(e)
+                return 1
+
+        cb = SINK(_sink)
+        r, h = _new_result(self._n[0])
+        rc = _lib().mce_enumerate_stream(self._h, int(chunk_verts), cb, None, ctypes.byref(r), _stream_ptr(stream))
+        if failure:
+            raise failure[0]
+        if rc not in (OK, E_CANCELLED):
+            raise MceError(rc, "mce_enumerate_stream")
+        out = _to_dict(r, h)
+        out["cancelled"] = rc == E_CANCELLED
+        return out
 
     def autotune(self, max_trials: int = 0, stream=None) -> dict:
         """mce_autotune: time candidate schedules on this handle and keep the

@@ -282,3 +282,44 @@ def test_pivot_rules_subproblem(mce, orc, rule, mode):
             same(g.count_subproblem([v], P, X), ref)
     finally:
         g.release()
+
+
+# ------------------------------------------------- streamed enumeration ---
+
+def test_enumerate_stream_matches_oracle_list(mce, orc):
+    """Chunks small enough to force many ranges, splits of ranges that
+    overflow, and one-child ranges with a grown buffer: the union of the
+    chunks is the oracle's clique list, the totals are the oracle's."""
+    rows = synth.gnp(120, 0.5, 2)
+    ref, ref_list = orc.greedy_list(rows)
+    g = mce.Graph(rows)
+    got, chunks = [], []
+    try:
+        def on_chunk(verts, pairs):
+            chunks.append(len(pairs))
+            got.extend(tuple(int(x) for x in verts[b:e]) for b, e in pairs)
+        res = g.enumerate_stream(on_chunk, chunk_verts=600)
+    finally:
+        g.release()
+    same(res, ref)
+    assert not res["cancelled"] and len(chunks) > 5 and sum(chunks) == ref["count"]
+    assert sorted(got) == sorted(ref_list)
+
+
+def test_enumerate_stream_cancel_and_empty(mce, orc):
+    rows = synth.gnp(120, 0.5, 2)
+    g = mce.Graph(rows)
+    seen = []
+    try:
+        res = g.enumerate_stream(lambda v, p: seen.append(len(p)) or len(seen) == 2, chunk_verts=600)
+    finally:
+        g.release()
+    assert res["cancelled"] and len(seen) == 2 and res["count"] == sum(seen) < orc.greedy(rows)["count"]
+    # n = 0: one chunk holding the empty clique
+    g = mce.Graph(synth.empty(0))
+    out = []
+    try:
+        res = g.enumerate_stream(lambda v, p: out.append((list(v), p.tolist())))
+    finally:
+        g.release()
+    assert res["count"] == 1 and out == [([], [[0, 0]])]
