@@ -629,10 +629,13 @@ struct WgHdr {
     uint32_t pool_left; // root units may be left in the pool
     uint32_t pool_size; // root units in the pool
     uint32_t rng;       // xorshift state for choosing whom to ask
-    uint32_t pad[4];
+    uint32_t hint;      // busy count last written to this workgroup's mailbox hint
+    uint32_t pad[3];
 };
 static_assert(sizeof(WgHdr) == kWgHdrWords * 4, "header size");
 constexpr uint32_t kOutReading = 0xffffffffu;
+// Workgroups whose busy hints an idle workgroup compares before asking one.
+constexpr uint32_t kAskSamples = 8;
 
 __device__ __forceinline__ uint32_t lds_ld(uint32_t* p)
 {
@@ -995,6 +998,11 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
     if (bcast0(refresh_v)) {
         uint32_t e = 0, rf = 0;
         if (lane == 0) {
+            // the busy count other workgroups see, written when it changed
+            if (lds_ld(&hdr->hint) != busy) {
+                st_dev(&sp.mail[blockIdx.x].hint, busy);
+                lds_st(&hdr->hint, busy);
+            }
             if (lds_ld(&hdr->req) == 0u) {
                 unsigned int* mreq = &sp.mail[blockIdx.x].req;
                 if (ld_dev(mreq) != 0u) {
@@ -1575,8 +1583,11 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
             wg_unlock(hdr, lane);
             fetch = bcast0(fetch);
             inactive = bcast0(inactive);
-            if (lane == 0 && went_inactive)
+            if (lane == 0 && went_inactive) {
                 __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st_dev(&sp.mail[me].hint, 0u);
+                lds_st(&hdr->hint, 0u);
+            }
             if (fetch) {
                 set_state(kWaveFetch);
                 uint32_t kind = 0, p = 0, stop_now = 0;
@@ -1619,15 +1630,29 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                             a = __hip_atomic_exchange(mreq, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (a != 0u) st_dev(&sp.mail[a - 1u].state, kMailRefused);
                     }
-                    // (d) ask a workgroup chosen at random
+                    // (d) ask a workgroup: of a few chosen at random, the one
+                    // whose hint shows the most busy wavefronts
                     if (kind == 0 && lds_ld(&hdr->out) == 0u && lds_ld(&hdr->pool_left) == 0u && sp.num_wg > 1u) {
                         uint32_t x = lds_ld(&hdr->rng);
-                        x ^= x << 13;
-                        x ^= x >> 17;
-                        x ^= x << 5;
+                        uint32_t cand[kAskSamples], hint[kAskSamples];
+#pragma unroll
+                        for (uint32_t t = 0; t < kAskSamples; t++) {
+                            x ^= x << 13;
+                            x ^= x >> 17;
+                            x ^= x << 5;
+                            uint32_t c = (uint32_t)(((uint64_t)x * (sp.num_wg - 1u)) >> 32);
+                            cand[t] = c >= me ? c + 1u : c;
+                        }
+#pragma unroll
+                        for (uint32_t t = 0; t < kAskSamples; t++) hint[t] = ld_dev(&sp.mail[cand[t]].hint);
                         lds_st(&hdr->rng, x);
-                        uint32_t v = (uint32_t)(((uint64_t)x * (sp.num_wg - 1u)) >> 32);
-                        if (v >= me) v++;
+                        uint32_t v = cand[0], vb = hint[0];
+#pragma unroll
+                        for (uint32_t t = 1; t < kAskSamples; t++)
+                            if (hint[t] > vb) {
+                                v = cand[t];
+                                vb = hint[t];
+                            }
                         uint32_t zero = 0u;
                         if (__hip_atomic_compare_exchange_strong(&sp.mail[v].req, &zero, me + 1u, __ATOMIC_RELAXED,
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -1669,6 +1694,10 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                     // the unit's count is already covered by this workgroup
                     if (lane == 0 && was_active)
                         __hip_atomic_fetch_sub(&sp.ctl->work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (lane == 0 && !was_active) {
+                        st_dev(&sp.mail[me].hint, 1u);
+                        lds_st(&hdr->hint, 1u);
+                    }
                     src = kind;
                     pos = p;
                     break;

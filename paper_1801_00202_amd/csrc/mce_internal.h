@@ -90,10 +90,13 @@ struct QueueCtl {
 // other workgroup at a time: it writes its id + 1 into that workgroup's req
 // word (compare-and-swap from 0), and the asked workgroup answers in the
 // asker's state word: a unit (copied to the asker's record slot first) or a
-// refusal.  Each word has a cache line of its own.
+// refusal.  The hint word says how many of the workgroup's wavefronts were
+// busy when it last looked (0 when it holds no work), so that askers can
+// prefer busy workgroups.  Each word has a cache line of its own.
 struct Mailbox {
     unsigned int req, pad_r[31];   // asking workgroup + 1, 0: none
     unsigned int state, pad_s[31]; // answer to this workgroup's own question
+    unsigned int hint, pad_b[31];  // busy wavefronts (a hint, written by the owner only)
 };
 constexpr unsigned int kMailNone = 0u, kMailUnit = 1u, kMailRefused = 2u;
 
