@@ -41,9 +41,23 @@ __device__ __forceinline__ uint32_t lane_id()
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Lanes whose x is non-zero, as a 64-bit mask (a compare into a scalar pair:
+// repeated tests of one word share it).
+__device__ __forceinline__ uint64_t nz_mask(uint32_t x) { return __builtin_amdgcn_uicmp(x, 0u, 33 /* ne */); }
+
 __device__ __forceinline__ uint32_t rdlane(uint32_t x, uint32_t l)
 {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+}
+
+// The write-lane operation (no clang builtin for it here): the compiler puts
+// the lane number in M0, as the instruction's operand rules require.
+__device__ int amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// x with lane l (uniform, below 64) replaced by the uniform value v.
+__device__ __forceinline__ uint32_t wrlane(uint32_t x, uint32_t v, uint32_t l)
+{
+    return (uint32_t)amdgcn_writelane((int)v, (int)l, (int)x);
 }
 
 __device__ __forceinline__ uint32_t bcast0(uint32_t x)
@@ -134,7 +148,7 @@ __device__ __forceinline__ bool any_set(const uint32_t (&s)[WPL])
     uint32_t o = s[0];
 #pragma unroll
     for (int c = 1; c < WPL; c++) o |= s[c];
-    return ballot(o != 0) != 0;
+    return nz_mask(o) != 0;
 }
 
 // Position of the lowest set bit, or -1 if the set is empty.
@@ -179,24 +193,37 @@ __device__ __forceinline__ int first_pos(const uint32_t (&s)[WPL], const uint32_
 {
 #pragma unroll
     for (int c = 0; c < WPL; c++) {
-        const uint64_t m = ballot(s[c] != 0u);
+        const uint64_t m = nz_mask(s[c]);
         if (m) {
-            const uint32_t pos = lane_lo[c] | (uint32_t)__builtin_ctzg(s[c], 32);
+            // only a lane with a set bit is read: no guard for an empty word
+            const uint32_t pos = lane_lo[c] | (uint32_t)__builtin_ctz(s[c]);
             return (int)rdlane(pos, (uint32_t)__builtin_ctzll(m));
         }
     }
     return -1;
 }
 
-// The one-bit mask of position v (uniform) in this lane's words.
+// Position of the lowest set bit of a set known to be non-empty.
 template <int WPL>
-__device__ __forceinline__ void bit_mask(uint32_t v, const uint32_t (&lane_lo)[WPL], uint32_t (&m)[WPL])
+__device__ __forceinline__ int first_pos_nz(const uint32_t (&s)[WPL], const uint32_t (&lane_lo)[WPL])
 {
-#pragma unroll
-    for (int c = 0; c < WPL; c++) {
-        const uint32_t d = v - lane_lo[c];
-        m[c] = d < 32u ? (1u << (d & 31u)) : 0u;
+    if (WPL == 1) {
+        const uint64_t m = nz_mask(s[0]);
+        const uint32_t pos = lane_lo[0] | (uint32_t)__builtin_ctz(s[0]);
+        return (int)rdlane(pos, (uint32_t)__builtin_ctzll(m));
     }
+    return first_pos<WPL>(s, lane_lo);
+}
+
+// The one-bit mask of position v (uniform) in this lane's words: the word
+// index and the bit are scalars, one compare and one select per word.
+// lane_w[c] = 64 c + lane.
+template <int WPL>
+__device__ __forceinline__ void bit_mask(uint32_t v, const uint32_t (&lane_w)[WPL], uint32_t (&m)[WPL])
+{
+    const uint32_t wi = v >> 5, b = 1u << (v & 31u);
+#pragma unroll
+    for (int c = 0; c < WPL; c++) m[c] = lane_w[c] == wi ? b : 0u;
 }
 
 // Inclusive prefix of popcounts over all words (chunk-major), and the total.
@@ -1104,12 +1131,13 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
     const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
         reinterpret_cast<void*>(abase), (short)0, (int)(gd.n * rs4), 0x00020000);
     const uint32_t* ord = sp.order + gd.ord_off;
-    uint32_t lane_lo[WPL], voff[WPL];
+    uint32_t lane_lo[WPL], lane_w[WPL], voff[WPL];
     bool live[WPL];
 #pragma unroll
     for (int c = 0; c < WPL; c++) {
         const uint32_t li = (uint32_t)c * 64u + lane;
         lane_lo[c] = li << 5;
+        lane_w[c] = li;
         voff[c] = li << 2;
         live[c] = li < W;
     }
@@ -1127,8 +1155,15 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
     const uint32_t SW = sp.slot_words, SPW = sp.spill_words;
     const uint32_t spill_levels = sp.spill_levels;
     GU32* const spill = (GU32*)(sp.spill);
-    uint32_t* stk = wl + kWaveFixedWords;
+    // the frame area's offset is hidden from the compiler, so that the frame
+    // address stays one vector register (not a register plus a constant that
+    // the paired LDS stores cannot encode)
+    uint32_t fixed = kWaveFixedWords;
+    asm volatile("" : "+s"(fixed));
+    uint32_t* stk = wl + fixed;
     uint32_t* cur = stk + (size_t)lds_depth * SW;
+    // this lane's words of frame 0 (frame s: + s * SW, chunk c: + 256 c)
+    uint32_t* const fl = stk + 4u * lane;
     uint32_t* buf = wl + kOffBuf;
     uint32_t* trash = wl + kOffTrash;
     uint32_t* save = wl + kOffSave;
@@ -1201,11 +1236,10 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             d--;
             uint32_t idp;
             if (d < lds_depth) {
-                const uint32_t* f = stk + (size_t)d * SW;
+                const uint32_t* f = fl + d * SW;
 #pragma unroll
                 for (int c = 0; c < WPL; c++) {
-                    const uint32_t li = (uint32_t)c * 64u + lane;
-                    const uint4 q = *reinterpret_cast<const uint4*>(f + 4u * li);
+                    const uint4 q = *reinterpret_cast<const uint4*>(f + 256u * c);
                     P[c] = live[c] ? q.x : 0u;
                     X[c] = live[c] ? q.y : 0u;
                     L[c] = live[c] ? q.z : 0u;
@@ -1227,27 +1261,18 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
                 load_row(cv >= 0 ? (uint32_t)cv : 0u, crow);
             }
             uint32_t m[WPL];
-            bit_mask<WPL>(idp, lane_lo, m);
+            bit_mask<WPL>(idp, lane_w, m);
 #pragma unroll
             for (int c = 0; c < WPL; c++) Rb[c] &= ~m[c];
             continue;
         }
-        // a push below the LDS window needs a spill chunk, and room in it
-        if (d >= lds_depth) {
-            if (chunk == 0xffffffffu) {
-                why = kUnitChunk;
-                break;
-            }
-            if (d - lds_depth >= spill_levels) {
-                why = kUnitDepth;
-                break;
-            }
-        }
+        // v is in L, L is a subset of P, and X is disjoint from P: taking v
+        // out of L and P and into X flips one bit in each
         const uint32_t v = (uint32_t)cv;
         uint32_t m[WPL];
-        bit_mask<WPL>(v, lane_lo, m);
+        bit_mask<WPL>(v, lane_w, m);
 #pragma unroll
-        for (int c = 0; c < WPL; c++) L[c] &= ~m[c];
+        for (int c = 0; c < WPL; c++) L[c] ^= m[c];
         // the next candidate's row is on its way while v is examined (with
         // no candidate left, row v again: a load on every path lets the wait
         // for crow below leave this one in flight)
@@ -1261,25 +1286,38 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             P2[c] = P[c] & crow[c];
             X2[c] = X[c] & crow[c];
             // steps 12-13 for the current node
-            P[c] &= ~m[c];
-            X[c] |= m[c];
+            P[c] ^= m[c];
+            X[c] ^= m[c];
         }
         kids++;
         if (any_set<WPL>(P2)) {
-            // the child is a node: push the current frame, descend
+            // the child is a node: push the current frame, descend.  A push
+            // below the LDS window needs a spill chunk and room in it; without
+            // them the child is put back (v into L and P, out of X) and
+            // examined again once the caller has made room.
+            if (d >= lds_depth && (chunk == 0xffffffffu || d - lds_depth >= spill_levels)) {
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    L[c] ^= m[c];
+                    P[c] ^= m[c];
+                    X[c] ^= m[c];
+                }
+                kids--;
+                why = chunk == 0xffffffffu ? kUnitChunk : kUnitDepth;
+                break;
+            }
             const uint32_t idv = row_id(crow, v);
             nodes++;
             const uint32_t dp = d;
             if (d < lds_depth) {
-                uint32_t* f = stk + (size_t)d * SW;
+                uint32_t* f = fl + d * SW;
 #pragma unroll
                 for (int c = 0; c < WPL; c++) {
-                    const uint32_t li = (uint32_t)c * 64u + lane;
-                    f[4 * li] = P[c];
-                    f[4 * li + 1] = X[c];
-                    f[4 * li + 2] = L[c];
+                    f[256 * c] = P[c];
+                    f[256 * c + 1] = X[c];
+                    f[256 * c + 2] = L[c];
                 }
-                idstk = (lane == d) ? idv : idstk;
+                idstk = wrlane(idstk, idv, d);
             } else {
                 GU32* fs = spill + ((size_t)chunk * spill_levels + (d - lds_depth)) * SPW;
 #pragma unroll
@@ -1294,7 +1332,7 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             }
             d++;
             uint32_t mi[WPL];
-            bit_mask<WPL>(idv, lane_lo, mi);
+            bit_mask<WPL>(idv, lane_w, mi);
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
                 Rb[c] |= mi[c];
@@ -1306,7 +1344,7 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             // with the pivot's: it is the first candidate whenever it is not
             // adjacent to the pivot (always when the pivot is that vertex).
             const int px = first_pos<WPL>(X, lane_lo);
-            const int pp = first_pos<WPL>(P, lane_lo);
+            const int pp = first_pos_nz<WPL>(P, lane_lo);
             uint32_t prow[WPL], frow[WPL];
             if (RULE == (int)kPivotGreedy || (RULE == (int)kPivotTX && px < 0)) {
                 const uint32_t piv = px >= 0 ? (uint32_t)px : (uint32_t)pp;
@@ -1334,7 +1372,7 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
                 bool have = false;
                 for (;;) {
                     uint32_t mu[WPL];
-                    bit_mask<WPL>((uint32_t)u, lane_lo, mu);
+                    bit_mask<WPL>((uint32_t)u, lane_w, mu);
 #pragma unroll
                     for (int c = 0; c < WPL; c++) C[c] &= ~mu[c];
                     const int nu = first_pos<WPL>(C, lane_lo);
@@ -1362,10 +1400,13 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             for (int c = 0; c < WPL; c++) L[c] = P[c] & ~prow[c];
             // the parent's next row, requested before the pivot's, is in:
             // keep it with the parent frame
-            if (dp < lds_depth && nv >= 0) {
-                uint32_t* f = stk + (size_t)dp * SW;
+            // (with no next candidate the slot is never read).  A frame in
+            // the spill pool keeps no row: the store then goes to the unused
+            // row slots of the current frame, which only a suspension writes.
+            {
+                uint32_t* f = fl + (dp < lds_depth ? dp : lds_depth) * SW;
 #pragma unroll
-                for (int c = 0; c < WPL; c++) f[4 * ((uint32_t)c * 64u + lane) + 3] = nrow[c];
+                for (int c = 0; c < WPL; c++) f[256 * c + 3] = nrow[c];
             }
             cv = first_pos<WPL>(L, lane_lo);
             if (cv == pp) {
@@ -1382,7 +1423,7 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
                 // more clique (it is emptied before it could run out).
                 const uint32_t idv = row_id(crow, v);
                 uint32_t mi[WPL];
-                bit_mask<WPL>(idv, lane_lo, mi);
+                bit_mask<WPL>(idv, lane_w, mi);
                 const uint32_t start = used;
 #pragma unroll
                 for (int c = 0; c < WPL; c++) {
@@ -1399,18 +1440,21 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
                     *(hi != 0u ? buf + phi : trash + lane) = ((hw + 1u) << 16) | hi;
                     used += (uint32_t)__builtin_popcountll(blo) + (uint32_t)__builtin_popcountll(bhi);
                 }
-                cent = (lane == nent) ? ((start << 16) | (used - start)) : cent;
+                cent = wrlane(cent, (start << 16) | (used - start), nent);
                 nent++;
-            }
-            cv = nv;
+                cv = nv;
 #pragma unroll
-            for (int c = 0; c < WPL; c++) crow[c] = nrow[c];
-        }
-
-        // a full clique buffer is emptied at once
-        if (nent == 64u || used + 2u * 64u * WPL > kCliqueSlots) {
-            why = kUnitFlush;
-            break;
+                for (int c = 0; c < WPL; c++) crow[c] = nrow[c];
+                // a full clique buffer is emptied at once
+                if (nent == 64u || used + 2u * 64u * WPL > kCliqueSlots) {
+                    why = kUnitFlush;
+                    break;
+                }
+            } else {
+                cv = nv;
+#pragma unroll
+                for (int c = 0; c < WPL; c++) crow[c] = nrow[c];
+            }
         }
         if (--budget == 0u) {
             // Look at the siblings and the workgroup's flags (LDS only);
