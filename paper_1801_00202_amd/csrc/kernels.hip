@@ -317,45 +317,67 @@ __global__ void validate_kernel(const uint64_t* rows, uint32_t n, uint32_t rw, u
 // Maximum-degree-first ordering (Sec. 4.2), one wavefront per graph.  Vertex v
 // belongs to lane v / KPL, slot v % KPL, and holds the key
 // (deg + 1) << 12 | (4095 - v): the wave maximum of the keys is the vertex of
-// largest remaining degree, ties to the smaller id.  Taken vertices hold 0.
+// largest remaining degree, ties to the smaller id.  Taken vertices hold 0 and
+// are out of the lane's mask of remaining vertices, so that a round costs one
+// maximum, one read of the chosen vertex's row chunk and one decrement per
+// slot.  The order is written 64 entries at a time from one register.  rows
+// is the graph's input rows (rw64 64-bit words each), in LDS or global memory.
 template <int KPL>
-__global__ void __launch_bounds__(64) order_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
-                                                   uint32_t* order)
+__device__ __forceinline__ void order_rounds(const GraphDesc& gd, const uint64_t* rows, uint32_t* ord)
 {
-    const GraphDesc gd = graphs[blockIdx.x];
+    using CT = typename std::conditional<KPL == 64, uint64_t, uint32_t>::type;
     const uint32_t n = gd.n;
-    if (n == 0) return;
     const uint32_t lane = lane_id();
-    const uint64_t* in = rows_in + gd.in_off;
     const uint32_t rs = gd.rw64;
     const uint32_t v0 = lane * KPL;
-    const uint32_t cw = v0 >> 6, csh = v0 & 63; // word and shift of this lane's row chunk
-    const uint64_t cmask = ~0ull >> (64 - KPL);
+    const CT cmask = (CT)(~0ull >> (64 - KPL));
+    // this lane's chunk of a row: word cw (of CT) at shift csh; a lane past n
+    // reads the row's last word (its slots are not in the mask)
+    const uint32_t rsw = KPL == 64 ? rs : 2u * rs;
+    const uint32_t cw = umin32(KPL == 64 ? lane : (v0 >> 5), rsw - 1u);
+    const uint32_t csh = KPL == 64 ? 0u : (v0 & 31u);
+    const CT* rw = reinterpret_cast<const CT*>(rows);
     uint32_t key[KPL];
+    CT alive = 0;
 #pragma unroll
     for (int j = 0; j < KPL; j++) {
         const uint32_t v = v0 + (uint32_t)j;
         uint32_t deg = 0;
         if (v < n)
-            for (uint32_t t = 0; t < rs; t++) deg += (uint32_t)__builtin_popcountll(in[(uint64_t)v * rs + t]);
+            for (uint32_t t = 0; t < rs; t++) deg += (uint32_t)__builtin_popcountll(rows[(uint64_t)v * rs + t]);
         key[j] = (v < n) ? (((deg + 1u) << 12) | (4095u - v)) : 0u;
+        alive |= (v < n) ? ((CT)1 << j) : (CT)0;
     }
-    uint32_t* ord = order + gd.ord_off;
+    uint32_t obuf = 0;
     for (uint32_t i = 0; i < n; i++) {
         uint32_t m = 0;
 #pragma unroll
         for (int j = 0; j < KPL; j++) m = umax32(m, key[j]);
         m = wave_max(m);
         const uint32_t v = 4095u - (m & 4095u);
-        if (lane == 0) ord[i] = v;
-        const uint64_t chunk = (v0 < n) ? ((in[(uint64_t)v * rs + cw] >> csh) & cmask) : 0ull;
-        const uint64_t vm = ((v / KPL) == lane) ? (1ull << (v % KPL)) : 0ull;
+        obuf = wrlane(obuf, v, i & 63u);
+        if ((i & 63u) == 63u || i + 1u == n) {
+            if (lane <= (i & 63u)) ord[(i & ~63u) + lane] = obuf;
+        }
+        const uint32_t lv = v / KPL, jv = v % KPL;
+        const CT nb = (CT)(rw[(uint64_t)v * rsw + cw] >> csh) & cmask & alive;
+        alive &= ~(lane == lv ? ((CT)1 << jv) : (CT)0);
 #pragma unroll
         for (int j = 0; j < KPL; j++) {
-            const bool nb = ((chunk >> j) & 1ull) && key[j] != 0u;
-            key[j] = ((vm >> j) & 1ull) ? 0u : (key[j] - (nb ? 4096u : 0u));
+            const int t = (int)__builtin_amdgcn_ubfe((uint32_t)(nb >> (j & ~31)), (uint32_t)(j & 31), 1u);
+            key[j] = (uint32_t)((int)key[j] + t * -4096);
         }
+        key[jv] = lane == lv ? 0u : key[jv];
     }
+}
+
+template <int KPL>
+__global__ void __launch_bounds__(64) order_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
+                                                   uint32_t* order)
+{
+    const GraphDesc gd = graphs[blockIdx.x];
+    if (gd.n == 0) return;
+    order_rounds<KPL>(gd, rows_in + gd.in_off, order + gd.ord_off);
 }
 
 // The same ordering with the graph's input rows staged in LDS first (when
@@ -369,40 +391,11 @@ __global__ void __launch_bounds__(64) order_lds_kernel(const GraphDesc* graphs, 
     const GraphDesc gd = graphs[blockIdx.x];
     const uint32_t n = gd.n;
     if (n == 0) return;
-    const uint32_t lane = lane_id();
     const uint64_t* in = rows_in + gd.in_off;
-    const uint32_t rs = gd.rw64;
-    const uint64_t words = (uint64_t)n * rs;
-    for (uint64_t i = lane; i < words; i += 64) rows_l[i] = in[i];
+    const uint64_t words = (uint64_t)n * gd.rw64;
+    for (uint64_t i = lane_id(); i < words; i += 64) rows_l[i] = in[i];
     __syncthreads();
-    const uint32_t v0 = lane * KPL;
-    const uint32_t cw = v0 >> 6, csh = v0 & 63; // word and shift of this lane's row chunk
-    const uint64_t cmask = ~0ull >> (64 - KPL);
-    uint32_t key[KPL];
-#pragma unroll
-    for (int j = 0; j < KPL; j++) {
-        const uint32_t v = v0 + (uint32_t)j;
-        uint32_t deg = 0;
-        if (v < n)
-            for (uint32_t t = 0; t < rs; t++) deg += (uint32_t)__builtin_popcountll(rows_l[(uint64_t)v * rs + t]);
-        key[j] = (v < n) ? (((deg + 1u) << 12) | (4095u - v)) : 0u;
-    }
-    uint32_t* ord = order + gd.ord_off;
-    for (uint32_t i = 0; i < n; i++) {
-        uint32_t m = 0;
-#pragma unroll
-        for (int j = 0; j < KPL; j++) m = umax32(m, key[j]);
-        m = wave_max(m);
-        const uint32_t v = 4095u - (m & 4095u);
-        if (lane == 0) ord[i] = v;
-        const uint64_t chunk = (v0 < n) ? ((rows_l[(uint64_t)v * rs + cw] >> csh) & cmask) : 0ull;
-        const uint64_t vm = ((v / KPL) == lane) ? (1ull << (v % KPL)) : 0ull;
-#pragma unroll
-        for (int j = 0; j < KPL; j++) {
-            const bool nb = ((chunk >> j) & 1ull) && key[j] != 0u;
-            key[j] = ((vm >> j) & 1ull) ? 0u : (key[j] - (nb ? 4096u : 0u));
-        }
-    }
+    order_rounds<KPL>(gd, rows_l, order + gd.ord_off);
 }
 
 // Renumbering (Sec. 4.2): row i of the new matrix is row order[i] of the input
