@@ -56,7 +56,7 @@
 #define ORC_E_INVAL (-1)
 #define ORC_E_NOMEM (-2)
 #define ORC_E_TRUNCATED (-3)
-#define ORC_MAX_N 4096u
+#define ORC_MAX_N 16384u
 
 typedef struct {
     uint64_t count;     /* number of maximal cliques */

@@ -31,9 +31,8 @@ def pack_rows(adj: np.ndarray) -> np.ndarray:
     rw = row_words(n)
     pad = np.zeros((n, rw * 64), dtype=bool)
     pad[:, :n] = adj
-    bits = pad.reshape(n, rw, 64).astype(np.uint64)
-    weights = (np.uint64(1) << np.arange(64, dtype=np.uint64))
-    return (bits * weights).sum(axis=2, dtype=np.uint64).reshape(n, rw)
+    b = np.packbits(pad, axis=1, bitorder="little")  # byte k of a row holds columns 8k..8k+7
+    return np.ascontiguousarray(b).view("<u8").astype(np.uint64).reshape(n, rw)
 
 
 def unpack_rows(rows: np.ndarray, n: int | None = None) -> np.ndarray:
@@ -53,8 +52,12 @@ def _pairs_to_adj(n: int, mask: np.ndarray) -> np.ndarray:
 
 def gnp(n: int, p: float, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
-    u = rng.random(n * (n - 1) // 2)
-    return pack_rows(_pairs_to_adj(n, u < p))
+    # the uniforms of row i's pairs (i, i+1..n-1) come next in the stream:
+    # drawing them row by row gives the same stream as one draw of all pairs
+    adj = np.zeros((n, n), dtype=bool)
+    for i in range(n - 1):
+        adj[i, i + 1:] = rng.random(n - 1 - i) < p
+    return pack_rows(adj | adj.T)
 
 
 def gnp_planted(n: int, p: float, seed: int, cliques: int = 12, lo: int = 20, hi: int = 40):
