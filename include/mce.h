@@ -16,7 +16,12 @@
  * edge.  Row i of a graph with n vertices has at least ceil(n/64) words.  The
  * graph must be simple: zero diagonal, symmetric, and no bit set at a column
  * >= n.  0 <= n <= MCE_MAX_N; n = 0 is allowed and has the single maximal
- * clique {} (count 1, hist[0] = 1, no search nodes).
+ * clique {} (count 1, hist[0] = 1, no search nodes).  Graphs of more than
+ * 4096 vertices (up to 16384, the sizes of the paper's Table 1 rows with
+ * n = 10^4) take the same method with bitsets of up to eight 32-bit words a
+ * lane; there a maximal clique whose ids fill more than 512 distinct groups
+ * of 16 consecutive ids (possible only for n > 8192) does not fit the
+ * per-wavefront clique buffer and the call returns MCE_E_NOMEM.
  *
  * Results (per graph): number of maximal cliques, a size histogram, the
  * number of search nodes ("steps" of the paper's tables: calls of Alg. 4 with
@@ -42,13 +47,14 @@
 extern "C" {
 #endif
 
-#define MCE_MAX_N 4096u
+#define MCE_MAX_N 16384u
 
 /* Status codes. */
 #define MCE_OK 0
 #define MCE_PENDING 1          /* mce_poll: the job has not finished yet */
 #define MCE_E_INVAL (-1)       /* bad argument or non-simple graph */
-#define MCE_E_NOMEM (-2)       /* device or host allocation failed */
+#define MCE_E_NOMEM (-2)       /* device or host allocation failed, or a clique too large for the
+                                  clique buffer (see above) */
 #define MCE_E_TRUNCATED (-3)   /* mce_enumerate: output buffer too small */
 #define MCE_E_DEVICE (-4)      /* HIP error, or no usable gfx950 device */
 #define MCE_E_BUSY (-5)        /* mce_submit: admission refused */

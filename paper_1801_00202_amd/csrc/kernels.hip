@@ -398,6 +398,63 @@ __global__ void __launch_bounds__(64) order_lds_kernel(const GraphDesc* graphs, 
     order_rounds<KPL>(gd, rows_l, order + gd.ord_off);
 }
 
+// The same ordering for graphs of up to kMaxN vertices: a workgroup of 16
+// wavefronts, 16 vertices a lane, keys (deg + 1) << 14 | (16383 - v).  Each
+// round the wavefronts' maxima meet in LDS (two slot rows in turn, so one
+// barrier a round suffices: a row is written again only after every
+// wavefront has passed the barrier that follows its last read) and every
+// wavefront takes the maximum of the 16.
+__global__ void __launch_bounds__(1024) order_wide_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
+                                                          uint32_t* order)
+{
+    constexpr int KPL = 16;
+    __shared__ uint32_t red[2][16];
+    const GraphDesc gd = graphs[blockIdx.x];
+    const uint32_t n = gd.n;
+    if (n == 0) return;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = bcast0(t >> 6);
+    const uint64_t* rows = rows_in + gd.in_off;
+    const uint32_t rs = gd.rw64, rsw = 2u * rs;
+    const uint32_t v0 = t * KPL;
+    // this thread's 16 bits of a row: 32-bit word cw at shift csh (a thread
+    // past n reads the row's last word; its slots are not in the mask)
+    const uint32_t cw = umin32(v0 >> 5, rsw - 1u), csh = v0 & 31u;
+    const uint32_t* rw = reinterpret_cast<const uint32_t*>(rows);
+    uint32_t key[KPL];
+    uint32_t alive = 0;
+#pragma unroll
+    for (int j = 0; j < KPL; j++) {
+        const uint32_t v = v0 + (uint32_t)j;
+        uint32_t deg = 0;
+        if (v < n)
+            for (uint32_t q = 0; q < rs; q++) deg += (uint32_t)__builtin_popcountll(rows[(uint64_t)v * rs + q]);
+        key[j] = (v < n) ? (((deg + 1u) << 14) | (16383u - v)) : 0u;
+        alive |= (v < n) ? (1u << j) : 0u;
+    }
+    uint32_t* ord = order + gd.ord_off;
+    uint32_t obuf = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int j = 0; j < KPL; j++) m = umax32(m, key[j]);
+        m = wave_max(m);
+        if (lane == 0) red[i & 1u][wave] = m;
+        __syncthreads();
+        m = wave_max(red[i & 1u][lane & 15u]);
+        const uint32_t v = 16383u - (m & 16383u);
+        if (wave == 0u) {
+            obuf = wrlane(obuf, v, i & 63u);
+            if (((i & 63u) == 63u || i + 1u == n) && lane <= (i & 63u)) ord[(i & ~63u) + lane] = obuf;
+        }
+        const uint32_t owner = v / KPL, jv = v % KPL;
+        const uint32_t nb = (rw[(uint64_t)v * rsw + cw] >> csh) & 0xffffu & alive;
+        alive &= ~(t == owner ? (1u << jv) : 0u);
+#pragma unroll
+        for (int j = 0; j < KPL; j++) key[j] -= ((nb >> j) & 1u) << 14;
+        key[jv] = t == owner ? 0u : key[jv];
+    }
+}
+
 // Renumbering (Sec. 4.2): row i of the new matrix is row order[i] of the input
 // with column j taken from column order[j].  Block (i, g), one word per thread.
 __global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
@@ -1083,7 +1140,8 @@ typedef const __attribute__((address_space(4))) GraphDesc CGraphDesc;
 typedef __attribute__((address_space(1))) uint32_t GU32;
 
 // Why search_unit returned.
-constexpr uint32_t kUnitDone = 0, kUnitAbort = 1, kUnitCheck = 2, kUnitFlush = 3, kUnitChunk = 4, kUnitDepth = 5;
+constexpr uint32_t kUnitDone = 0, kUnitAbort = 1, kUnitCheck = 2, kUnitFlush = 3, kUnitChunk = 4, kUnitDepth = 5,
+                   kUnitBig = 6;
 
 // The search of one unit (R, P, X, L) of graph g by one wavefront: Alg. 4
 // from that node, branching only on the candidates in L.  The loop calls no
@@ -1138,7 +1196,7 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
     auto row_id = [&](const uint32_t (&r)[WPL], uint32_t v) -> uint32_t {
         if (WPL == 1) return rdlane(r[0], W);
         if (W < 64u) return rdlane(r[0], W);
-        if (W < 128u) return rdlane(r[WPL - 1], W - 64u);
+        if (W < 128u) return rdlane(r[1], W - 64u);
         return bcast0(ord[v]);
     };
     (void)ord;
@@ -1412,26 +1470,48 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             if (!any_set<WPL>(X2)) {
                 // P' and X' empty: R u {v} is maximal.  R is the bitset Rb over
                 // input ids; its non-empty 16-bit halves, in lane order, are the
-                // clique's sorted ids.  The buffer always has room for one
-                // more clique (it is emptied before it could run out).
+                // clique's sorted ids.  A clique has at most 2 W of them: up to
+                // four chunks the buffer is emptied whenever fewer than 2 W
+                // slots are left; wider graphs count the clique's halves first
+                // and, when they do not fit, put the child back and empty the
+                // buffer (a clique larger than the whole buffer is an error).
                 const uint32_t idv = row_id(crow, v);
-                uint32_t mi[WPL];
+                uint32_t mi[WPL], cwd[WPL];
+                uint64_t blo[WPL], bhi[WPL];
+                uint32_t halves = 0;
                 bit_mask<WPL>(idv, lane_w, mi);
+#pragma unroll
+                for (int c = 0; c < WPL; c++) {
+                    cwd[c] = Rb[c] | mi[c];
+                    blo[c] = ballot((cwd[c] & 0xffffu) != 0u);
+                    bhi[c] = ballot((cwd[c] >> 16) != 0u);
+                    halves += (uint32_t)__builtin_popcountll(blo[c]) + (uint32_t)__builtin_popcountll(bhi[c]);
+                }
+                if (WPL >= 4 && used + halves > kCliqueSlots) {
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) {
+                        L[c] ^= m[c];
+                        P[c] ^= m[c];
+                        X[c] ^= m[c];
+                    }
+                    kids--;
+                    why = used == 0u ? kUnitBig : kUnitFlush;
+                    break;
+                }
                 const uint32_t start = used;
 #pragma unroll
                 for (int c = 0; c < WPL; c++) {
-                    const uint32_t cw = Rb[c] | mi[c];
-                    const uint32_t lo = cw & 0xffffu, hi = cw >> 16;
-                    const uint64_t blo = ballot(lo != 0u), bhi = ballot(hi != 0u);
-                    const uint32_t below =
-                        __builtin_amdgcn_mbcnt_hi((uint32_t)(blo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)blo, 0u)) +
-                        __builtin_amdgcn_mbcnt_hi((uint32_t)(bhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bhi, 0u));
+                    const uint32_t lo = cwd[c] & 0xffffu, hi = cwd[c] >> 16;
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                               (uint32_t)(blo[c] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)blo[c], 0u)) +
+                                           __builtin_amdgcn_mbcnt_hi(
+                                               (uint32_t)(bhi[c] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bhi[c], 0u));
                     const uint32_t plo = used + below;
                     const uint32_t phi = plo + (lo != 0u ? 1u : 0u);
                     const uint32_t hw = (((uint32_t)c * 64u + lane) << 1);
                     *(lo != 0u ? buf + plo : trash + lane) = (hw << 16) | lo;
                     *(hi != 0u ? buf + phi : trash + lane) = ((hw + 1u) << 16) | hi;
-                    used += (uint32_t)__builtin_popcountll(blo) + (uint32_t)__builtin_popcountll(bhi);
+                    used += (uint32_t)__builtin_popcountll(blo[c]) + (uint32_t)__builtin_popcountll(bhi[c]);
                 }
                 cent = wrlane(cent, (start << 16) | (used - start), nent);
                 nent++;
@@ -1439,7 +1519,7 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
 #pragma unroll
                 for (int c = 0; c < WPL; c++) crow[c] = nrow[c];
                 // a full clique buffer is emptied at once
-                if (nent == 64u || used + 2u * 64u * WPL > kCliqueSlots) {
+                if (nent == 64u || (WPL < 4 && used + 2u * W > kCliqueSlots)) {
                     why = kUnitFlush;
                     break;
                 }
@@ -1495,7 +1575,8 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
 }
 
 template <int WPL, int RULE>
-__global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const SearchParams* __restrict__ spp)
+__global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(SearchParams sp,
+                                                                         const SearchParams* __restrict__ spp)
 {
     // sp (by value) serves the hot path, where its pointers are known to be
     // global; spp, the same block in HBM, is handed to the out-of-line helpers.
@@ -1821,6 +1902,7 @@ __global__ void __launch_bounds__(1024) search_kernel(SearchParams sp, const Sea
                 abort = bcast0(cold_spill_chunk(spp, wl)) == 0xffffffffu;
             } else {
                 if (why == kUnitDepth) cold_error(spp, kErrDepth);
+                if (why == kUnitBig) cold_error(spp, kErrClique);
                 abort = true;
             }
             if (abort) break;
@@ -1912,7 +1994,9 @@ hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t m
             hipLaunchKernelGGL(order_lds_kernel<32>, dim3(num_graphs), dim3(64), lds, s, graphs, rows_in, order);
         return hipGetLastError();
     }
-    if (max_n <= 512)
+    if (max_n > 4096)
+        hipLaunchKernelGGL(order_wide_kernel, dim3(num_graphs), dim3(1024), 0, s, graphs, rows_in, order);
+    else if (max_n <= 512)
         hipLaunchKernelGGL(order_kernel<8>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
     else if (max_n <= 1024)
         hipLaunchKernelGGL(order_kernel<16>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
@@ -1955,12 +2039,23 @@ hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max
     // writers per graph: enough to fill the queue quickly, few per graph in a batch
     uint32_t k = 1;
     while (k < 64 && k < max_units && (uint64_t)num_graphs * k < 4096) k <<= 1;
-    if (max_w32 <= 64) {
+    switch (search_chunks(max_w32)) {
+    case 1:
         hipLaunchKernelGGL(root_plan_kernel<1>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
         hipLaunchKernelGGL(root_units_kernel<1>, dim3(num_graphs, k), dim3(64), 0, s, sp, first, last);
-    } else {
+        break;
+    case 2:
         hipLaunchKernelGGL(root_plan_kernel<2>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
         hipLaunchKernelGGL(root_units_kernel<2>, dim3(num_graphs, k), dim3(64), 0, s, sp, first, last);
+        break;
+    case 4:
+        hipLaunchKernelGGL(root_plan_kernel<4>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
+        hipLaunchKernelGGL(root_units_kernel<4>, dim3(num_graphs, k), dim3(64), 0, s, sp, first, last);
+        break;
+    default:
+        hipLaunchKernelGGL(root_plan_kernel<8>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
+        hipLaunchKernelGGL(root_units_kernel<8>, dim3(num_graphs, k), dim3(64), 0, s, sp, first, last);
+        break;
     }
     return hipGetLastError();
 }
@@ -1968,23 +2063,36 @@ hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max
 hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uint32_t* bits, hipStream_t s)
 {
     (void)hipGetLastError(); // report only this call's launch errors
-    if (max_w32 <= 64)
-        hipLaunchKernelGGL(subproblem_kernel<1>, dim3(1), dim3(64), 0, s, sp, bits);
-    else
-        hipLaunchKernelGGL(subproblem_kernel<2>, dim3(1), dim3(64), 0, s, sp, bits);
+    switch (search_chunks(max_w32)) {
+    case 1: hipLaunchKernelGGL(subproblem_kernel<1>, dim3(1), dim3(64), 0, s, sp, bits); break;
+    case 2: hipLaunchKernelGGL(subproblem_kernel<2>, dim3(1), dim3(64), 0, s, sp, bits); break;
+    case 4: hipLaunchKernelGGL(subproblem_kernel<4>, dim3(1), dim3(64), 0, s, sp, bits); break;
+    default: hipLaunchKernelGGL(subproblem_kernel<8>, dim3(1), dim3(64), 0, s, sp, bits); break;
+    }
     return hipGetLastError();
 }
 
 typedef void (*SearchFn)(SearchParams, const SearchParams*);
 
+template <int RULE>
+static SearchFn search_fn_rule(uint32_t chunks)
+{
+    switch (chunks) {
+    case 1: return search_kernel<1, RULE>;
+    case 2: return search_kernel<2, RULE>;
+    case 4: return search_kernel<4, RULE>;
+    default: return search_kernel<8, RULE>;
+    }
+}
+
 // The search kernel for a bitset width (chunks per lane) and a pivot rule.
 static SearchFn search_fn(uint32_t max_w32, uint32_t rule)
 {
-    const bool one = search_chunks(max_w32) == 1;
+    const uint32_t chunks = search_chunks(max_w32);
     switch (rule) {
-    case kPivotTomita: return one ? search_kernel<1, kPivotTomita> : search_kernel<2, kPivotTomita>;
-    case kPivotTX: return one ? search_kernel<1, kPivotTX> : search_kernel<2, kPivotTX>;
-    default: return one ? search_kernel<1, kPivotGreedy> : search_kernel<2, kPivotGreedy>;
+    case kPivotTomita: return search_fn_rule<kPivotTomita>(chunks);
+    case kPivotTX: return search_fn_rule<kPivotTX>(chunks);
+    default: return search_fn_rule<kPivotGreedy>(chunks);
     }
 }
 
@@ -1997,7 +2105,7 @@ static hipError_t ensure_search_attr()
         int dev = 0, lds = 0;
         err = hipGetDevice(&dev);
         if (err == hipSuccess) err = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        for (uint32_t w32 : {1u, 2u * kOneChunkMaxW32})
+        for (uint32_t w32 : {1u, 127u, 255u, kMaxN / 32u})
             for (uint32_t rule : {kPivotGreedy, kPivotTomita, kPivotTX})
                 if (err == hipSuccess)
                     err = hipFuncSetAttribute((const void*)search_fn(w32, rule),

@@ -7,7 +7,7 @@
 
 namespace mce {
 
-constexpr uint32_t kMaxN = 4096;
+constexpr uint32_t kMaxN = 16384;
 // Per-wavefront clique buffer in LDS: each buffered clique is the list of the
 // non-empty 16-bit halves of its input-id bitset, one word per half
 // (half index << 16 | bits), in increasing order; at most 64 cliques.
@@ -28,9 +28,17 @@ constexpr uint32_t kWaveFixedWords = kHistLds * 2 + kCliqueSlots + 64 + 32 + 128
 
 // Wavefront-lane layout of the search: one 32-bit word per lane and chunk.
 // A graph with w32 + 1 <= 64 row words (n <= 2016) uses one chunk, larger ones
-// two (the +1 is the input-id word of a row).
+// two (the +1 is the input-id word of a row, read while w32 < 128), then four
+// (n <= 8160) and eight (n <= kMaxN).
 constexpr uint32_t kOneChunkMaxW32 = 63;
-inline uint32_t search_chunks(uint32_t max_w32) { return max_w32 <= kOneChunkMaxW32 ? 1u : 2u; }
+inline uint32_t search_chunks(uint32_t max_w32)
+{
+    return max_w32 <= kOneChunkMaxW32 ? 1u : max_w32 <= 127u ? 2u : max_w32 <= 255u ? 4u : 8u;
+}
+
+// Wavefronts per search workgroup at most: four for the wide layouts, whose
+// registers per lane would not fit four wavefronts per SIMD.
+constexpr uint32_t max_search_wpb(uint32_t chunks) { return chunks >= 4u ? 4u : 16u; }
 
 // LDS stack frame (P, X, L and the row of the frame's next candidate,
 // interleaved per lane, 16 bytes a lane): words per frame, and the slack after
@@ -39,7 +47,7 @@ inline uint32_t search_chunks(uint32_t max_w32) { return max_w32 <= kOneChunkMax
 // w32) is kept.
 inline uint32_t lds_frame_words(uint32_t max_w32)
 {
-    return search_chunks(max_w32) == 1 ? 4u * (max_w32 + 1u) : 512u;
+    return search_chunks(max_w32) == 1 ? 4u * (max_w32 + 1u) : 256u * search_chunks(max_w32);
 }
 inline uint32_t lds_slack_words(uint32_t max_w32)
 {
@@ -104,6 +112,8 @@ constexpr unsigned int kMailNone = 0u, kMailUnit = 1u, kMailRefused = 2u;
 constexpr unsigned int kErrSpill = 1u; // spill pool exhausted: rerun with a larger pool
 constexpr unsigned int kErrDepth = 2u; // stack deeper than a spill chunk: rerun with chunks of full depth
 constexpr unsigned int kErrWatchdog = 4u; // the search ran past its deadline
+constexpr unsigned int kErrClique = 8u;   // a clique with more non-empty 16-bit id groups than the
+                                          // clique buffer's slots (only possible for n > 8192)
 
 struct SearchParams {
     const GraphDesc* graphs;

@@ -350,6 +350,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     // an explicit option wins, then the handle's tuned choice, then the default
     c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16)
                                   : (h->tune.wpb ? h->tune.wpb : 8u);
+    c.wpb = std::min<uint32_t>(c.wpb, max_search_wpb(search_chunks(h->max_w32)));
     c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
     c.rule = (uint32_t)o.pivot;
     c.slot_words = lds_frame_words(c.w32cap);
@@ -636,6 +637,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
             g->spill_full_depth = full_depth;
             continue;
         }
+        if (ctl.error & kErrClique) return MCE_E_NOMEM;
         if (ctl.error) return MCE_E_DEVICE;
         if (ctl_out) *ctl_out = ctl;
         float ms = 0.f;

@@ -26,7 +26,7 @@ E_DEVICE = -4
 E_BUSY = -5
 E_CANCELLED = -6
 F_DEVICE_PTR = 0x1
-MAX_N = 4096
+MAX_N = 16384
 
 OPTIONS = {
     "waves_per_block": 1,

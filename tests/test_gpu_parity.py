@@ -80,6 +80,39 @@ def test_large_n_two_words_per_lane(mce, orc):
         g.release()
 
 
+@pytest.mark.parametrize("n,p,seed", [(4097, 0.003, 4), (6000, 0.002, 5), (8161, 0.001, 6),
+                                      (10000, 0.001, 7), (16384, 0.0005, 8)])
+def test_wide_rows(mce, orc, n, p, seed):
+    # n > 4096: four (w32 <= 255) or eight 32-bit words a lane, the
+    # sixteen-wavefront ordering; n = 10^4, p = 0.001 is a Table 1 row
+    rows = synth.gnp(n, p, seed)
+    res, g = solve(mce, rows)
+    assert list(g.order()) == list(orc.order(rows))
+    same(res, orc.greedy(rows, threads=8))
+    g.release()
+
+
+def test_wide_special_graphs(mce, orc):
+    # a 5000-deep chain of single-child nodes (spilled stack, one clique of
+    # 5000 ids in 313 groups) and 10^4 isolated vertices
+    for rows in (synth.complete(5000), synth.empty(10000)):
+        res, g = solve(mce, rows)
+        same(res, orc.greedy(rows))
+        g.release()
+
+
+def test_wide_clique_too_large(mce):
+    # K_9000: its one clique has 563 non-empty 16-bit id groups, more than the
+    # 512 slots of a wavefront's clique buffer
+    g = mce.Graph(synth.complete(9000))
+    try:
+        with pytest.raises(mce.MceError) as e:
+            g.count()
+        assert e.value.code == mce.E_NOMEM
+    finally:
+        g.release()
+
+
 def test_range_sums(mce, orc):
     rows = synth.gnp(150, 0.5, 3)
     g = mce.Graph(rows)
