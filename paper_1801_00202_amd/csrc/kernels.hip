@@ -403,7 +403,10 @@ __global__ void __launch_bounds__(64) order_lds_kernel(const GraphDesc* graphs, 
 // round the wavefronts' maxima meet in LDS (two slot rows in turn, so one
 // barrier a round suffices: a row is written again only after every
 // wavefront has passed the barrier that follows its last read) and every
-// wavefront takes the maximum of the 16.
+// wavefront takes the maximum of the 16.  The row chunk of the runner-up
+// (the largest of the other 15 wavefront maxima, the next round's choice
+// unless it is a neighbour of this round's or its wavefront's next maximum
+// is larger) is requested one round ahead.
 __global__ void __launch_bounds__(1024) order_wide_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
                                                           uint32_t* order)
 {
@@ -433,25 +436,43 @@ __global__ void __launch_bounds__(1024) order_wide_kernel(const GraphDesc* graph
     }
     uint32_t* ord = order + gd.ord_off;
     uint32_t obuf = 0;
-    for (uint32_t i = 0; i < n; i++) {
-        uint32_t m = 0;
+    uint32_t pre_v = 0xffffffffu, pre_w = 0;
+    // a wavefront none of whose vertices lost a neighbour or was taken keeps
+    // its maximum from the previous round (most of them, on sparse graphs)
+    uint32_t wmax = 0;
 #pragma unroll
-        for (int j = 0; j < KPL; j++) m = umax32(m, key[j]);
-        m = wave_max(m);
-        if (lane == 0) red[i & 1u][wave] = m;
+    for (int j = 0; j < KPL; j++) wmax = umax32(wmax, key[j]);
+    wmax = wave_max(wmax);
+    for (uint32_t i = 0; i < n; i++) {
+        if (lane == 0) red[i & 1u][wave] = wmax;
         __syncthreads();
-        m = wave_max(red[i & 1u][lane & 15u]);
+        const uint32_t wm = red[i & 1u][lane & 15u];
+        const uint32_t m = wave_max(wm);
         const uint32_t v = 16383u - (m & 16383u);
+        const uint32_t m2 = wave_max(wm == m ? 0u : wm);
+        const uint32_t word = v == pre_v ? pre_w : rw[(uint64_t)v * rsw + cw];
+        if (m2 != 0u) {
+            pre_v = 16383u - (m2 & 16383u);
+            pre_w = rw[(uint64_t)pre_v * rsw + cw];
+        } else {
+            pre_v = 0xffffffffu;
+        }
         if (wave == 0u) {
             obuf = wrlane(obuf, v, i & 63u);
             if (((i & 63u) == 63u || i + 1u == n) && lane <= (i & 63u)) ord[(i & ~63u) + lane] = obuf;
         }
         const uint32_t owner = v / KPL, jv = v % KPL;
-        const uint32_t nb = (rw[(uint64_t)v * rsw + cw] >> csh) & 0xffffu & alive;
-        alive &= ~(t == owner ? (1u << jv) : 0u);
+        const uint32_t nb = (word >> csh) & 0xffffu & alive;
+        if (ballot(nb != 0u || t == owner) != 0u) {
+            alive &= ~(t == owner ? (1u << jv) : 0u);
 #pragma unroll
-        for (int j = 0; j < KPL; j++) key[j] -= ((nb >> j) & 1u) << 14;
-        key[jv] = t == owner ? 0u : key[jv];
+            for (int j = 0; j < KPL; j++) key[j] -= ((nb >> j) & 1u) << 14;
+            key[jv] = t == owner ? 0u : key[jv];
+            uint32_t lm = 0;
+#pragma unroll
+            for (int j = 0; j < KPL; j++) lm = umax32(lm, key[j]);
+            wmax = wave_max(lm);
+        }
     }
 }
 
