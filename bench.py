@@ -127,6 +127,40 @@ def batched(mce, synth, np, reps: int, tune: bool) -> dict:
             "vs_plain": dt_plain / dt}
 
 
+# Table 1, GreedyBB columns at n = 10^4 (mean of 10 graphs on one Xeon
+# E5-2690 v2 core): p -> (maximal cliques, steps, seconds)
+PAPER_N10K = {0.001: (50.006e3, 7.434e3, 0.034), 0.003: (142.630e3, 13.242e3, 0.082),
+              0.005: (215.789e3, 28.616e3, 0.133), 0.010: (349.705e3, 137.628e3, 0.299),
+              0.030: (3.746762e6, 1.440393e6, 2.316)}
+
+
+def table1_n10k(mce, synth, np, reps: int) -> dict:
+    """The n = 10^4 rows of Table 1 (G(10^4, p), seed 0; eight 32-bit words a
+    lane): whole job per graph, from the device rows to the result (handle,
+    ordering, renumbering, search), best of reps."""
+    import torch
+    out = {}
+    for p, (mu, steps, sec) in PAPER_N10K.items():
+        rows = synth.gnp(10000, p, 0)
+        d = torch.from_numpy(rows.view(np.int64)).cuda()
+        torch.cuda.synchronize()
+        best, res, st = None, None, None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            g = mce.Graph(d)
+            res = g.count()
+            dt = time.perf_counter() - t0
+            st = mce.last_stats()
+            g.release()
+            best = dt if best is None else min(best, dt)
+        out["p=%g" % p] = {"ms": best * 1e3, "search_kernel_ms": st["search_kernel_us"] / 1e3,
+                           "cliques": res["count"], "nodes": res["nodes"], "omega": res["omega"],
+                           "cliques_per_s": res["count"] / best,
+                           "paper": {"cliques": mu, "steps": steps, "seconds": sec,
+                                     "time_ratio": sec / best}}
+    return out
+
+
 def serving(mce, synth, np, count: int, warm: int) -> dict:
     """Requests from the serving mix (n log-uniform in [64, 2048], p ~ U[0.2,
     0.9], E[mu] <= 1e6), prepared on the device beforehand, submitted with
@@ -233,6 +267,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rules", action="store_true", help="skip the pivot-rule comparison")
     ap.add_argument("--no-enumerate", action="store_true", help="skip the streamed enumeration")
+    ap.add_argument("--no-table1", action="store_true", help="skip the n = 10^4 rows of Table 1")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="automatic schedule instead of mce_autotune's")
     ap.add_argument("--opts", default="", metavar="K=V,...",
@@ -347,6 +382,8 @@ def main():
         line["pivot_rules"] = pivot_rules(mce, d_rows, reps=3)
     if not args.no_enumerate:
         line["enumerate_stream"] = streamed_enumerate(mce, d_rows)
+    if not args.no_table1:
+        line["table1_n10k"] = table1_n10k(mce, synth, np, reps=3)
     if not args.no_batch:
         line["batched"] = batched(mce, synth, np, reps=3, tune=not args.no_tune)
     if not args.no_serving:
