@@ -92,6 +92,55 @@ def test_wide_rows(mce, orc, n, p, seed):
     g.release()
 
 
+@pytest.mark.parametrize("rule", ("tomita_bb", "greedy_tx"))
+def test_wide_pivot_rules(mce, orc, rule):
+    # the other pivot rules on the four- and eight-word layouts
+    for n, p, seed in [(5000, 0.004, 21), (9000, 0.001, 22)]:
+        rows = synth.gnp(n, p, seed)
+        mce.set_option("pivot", mce.PIVOT_RULES[rule])
+        res, g = solve(mce, rows)
+        same(res, orc.solve_rule(rows, rule))
+        g.release()
+
+
+def test_wide_batch_and_ranges(mce, orc):
+    # one handle holding wide and small graphs (all run the eight-word layout
+    # and the sixteen-wavefront ordering), then root-child ranges of a wide graph
+    graphs = [synth.gnp(9000, 0.001, 23), synth.gnp(100, 0.5, 24), synth.gnp(5000, 0.003, 25),
+              synth.complete(40), synth.empty(0)]
+    b = mce.Graph(batch=graphs)
+    try:
+        out = b.count()
+        for i, rows in enumerate(graphs):
+            same(out[i], orc.greedy(rows))
+            if rows.shape[0]:
+                assert list(b.order(i)) == list(orc.order(rows))
+    finally:
+        b.release()
+    rows = graphs[0]
+    g = mce.Graph(rows)
+    try:
+        nb = g.root_branches()
+        a, c = nb // 3, 2 * nb // 3
+        same(g.count_range(a, c), orc.greedy_range(rows, a, c))
+    finally:
+        g.release()
+
+
+def test_wide_enumerate_stream(mce, orc):
+    rows = synth.gnp(6000, 0.002, 26)
+    ref, ref_list = orc.greedy_list(rows)
+    g = mce.Graph(rows)
+    got = []
+    try:
+        res = g.enumerate_stream(lambda verts, pairs: got.extend(
+            tuple(int(x) for x in verts[b:e]) for b, e in pairs), chunk_verts=20000)
+    finally:
+        g.release()
+    same(res, ref)
+    assert sorted(got) == sorted(ref_list)
+
+
 def test_wide_special_graphs(mce, orc):
     # a 5000-deep chain of single-child nodes (spilled stack, one clique of
     # 5000 ids in 313 groups) and 10^4 isolated vertices
