@@ -197,6 +197,62 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host blocks, cached by power-of-two size like the device blocks
+// (handles are made and released per solve; hipHostMalloc and hipHostFree
+// cost tens of microseconds each).  At most kPinnedCacheBytes stay cached.
+constexpr size_t kPinnedCacheBytes = 256ull << 20;
+
+struct PinnedPool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free_blocks;
+    size_t cached = 0;
+};
+
+PinnedPool& pinned_pool()
+{
+    static PinnedPool* p = new PinnedPool(); // never destroyed: HIP may be torn down first at exit
+    return *p;
+}
+
+void* pinned_alloc(size_t want, size_t* got)
+{
+    const size_t sz = pool_round(want);
+    PinnedPool& pl = pinned_pool();
+    {
+        std::lock_guard<std::mutex> lk(pl.mu);
+        auto it = pl.free_blocks.find(sz);
+        if (it != pl.free_blocks.end()) {
+            void* p = it->second;
+            pl.free_blocks.erase(it);
+            pl.cached -= sz;
+            *got = sz;
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    *got = sz;
+    return p;
+}
+
+void pinned_free(void* p, size_t sz)
+{
+    if (!p) return;
+    PinnedPool& pl = pinned_pool();
+    {
+        std::lock_guard<std::mutex> lk(pl.mu);
+        if (pl.cached + sz <= kPinnedCacheBytes) {
+            pl.free_blocks.emplace(sz, p);
+            pl.cached += sz;
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+}
+
 struct HostPinned {
     void* p = nullptr;
     size_t bytes = 0;
@@ -206,7 +262,7 @@ struct HostPinned {
     ~HostPinned() { reset(); }
     void reset()
     {
-        if (p) (void)hipHostFree(p);
+        pinned_free(p, bytes);
         p = nullptr;
         bytes = 0;
     }
@@ -214,12 +270,11 @@ struct HostPinned {
     {
         if (want <= bytes && p) return MCE_OK;
         reset();
-        if (want == 0) want = 8;
-        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
-            p = nullptr;
+        p = pinned_alloc(want ? want : 8, &bytes);
+        if (!p) {
+            bytes = 0;
             return MCE_E_NOMEM;
         }
-        bytes = want;
         return MCE_OK;
     }
 };
