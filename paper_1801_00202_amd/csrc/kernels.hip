@@ -1017,7 +1017,9 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                 Ls[c] = (w < W) ? *fword(s, c, 2) : 0u;
             }
             const uint32_t tot = popc_scan<WPL>(Ls, cnt, incl);
-            if (tot < 2) {
+            // an ancestor frame gives even its last candidate (the owner keeps
+            // the subtree it is in); the current frame keeps half of its own
+            if (tot < (s == d ? 2u : 1u)) {
                 s++;
                 continue;
             }
@@ -1031,7 +1033,7 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
             }
             // frames below are smaller still
             if (wave_sum(pc) < sp.split_threshold) break;
-            const uint32_t keep = (tot + 1u) / 2u;
+            const uint32_t keep = s == d ? (tot + 1u) / 2u : tot / 2u;
             uint32_t L1[WPL], L2[WPL], Pd[WPL], Xd[WPL], Rs[WPL];
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
