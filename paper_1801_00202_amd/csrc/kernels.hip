@@ -29,6 +29,10 @@
 
 #include <mutex>
 
+// The write-lane operation (no clang builtin for it here): the compiler puts
+// the lane number in M0, as the instruction's operand rules require.
+__device__ int amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace mce {
 namespace {
 
@@ -49,10 +53,6 @@ __device__ __forceinline__ uint32_t rdlane(uint32_t x, uint32_t l)
 {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
 }
-
-// The write-lane operation (no clang builtin for it here): the compiler puts
-// the lane number in M0, as the instruction's operand rules require.
-__device__ int amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 // x with lane l (uniform, below 64) replaced by the uniform value v.
 __device__ __forceinline__ uint32_t wrlane(uint32_t x, uint32_t v, uint32_t l)
