@@ -233,18 +233,22 @@ def test_batch_matches_single(mce, orc):
     {"lds_depth": 1, "check_interval": 1, "split_threshold": 1 << 20},
     {"waves_per_block": 1, "blocks": 3},
     {"check_interval": 1, "split_threshold": 1 << 20, "queue_cap": 64},
+    # every look splits whatever it can, ancestors' last candidates included
+    {"check_interval": 1, "split_threshold": 1},
+    {"check_interval": 2, "split_threshold": 1, "lds_depth": 1, "waves_per_block": 2},
     pytest.param({"waves_per_block": 16, "lds_depth": 2}, marks=pytest.mark.skip(
         reason="stalled past the test timeout once (16 wavefronts per workgroup, LDS depth 2, "
                "spill-pool retry); cause not yet shown, kept off the GPU until it is")),
 ])
 def test_schedule_stress(mce, orc, opts):
-    rows = synth.gnp(120, 0.6, 11)
-    ref = orc.greedy(rows)
     for k, v in opts.items():
         mce.set_option(k, v)
-    res, g = solve(mce, rows)
-    same(res, ref)
-    g.release()
+    # a random graph and a chain-like tree (one or two candidates per node)
+    for rows in (synth.gnp(120, 0.6, 11), synth.moon_moser(9)):
+        ref = orc.greedy(rows)
+        res, g = solve(mce, rows)
+        same(res, ref)
+        g.release()
 
 
 def test_repeat_determinism(mce):
