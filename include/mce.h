@@ -67,7 +67,9 @@ extern "C" {
  * made after the change; 0 restores the automatic choice where noted. */
 #define MCE_OPT_WAVES_PER_BLOCK 1  /* search wavefronts per workgroup, 1..16 (0 = auto) */
 #define MCE_OPT_BLOCKS 2           /* persistent search workgroups (0 = fill the device) */
-#define MCE_OPT_LDS_DEPTH 3        /* stack levels kept in LDS per wavefront, 0..64 (rest spill to HBM) */
+#define MCE_OPT_LDS_DEPTH 3        /* stack levels kept in LDS per wavefront, 0..64 (rest spill to HBM);
+                                      with 16 wavefronts a workgroup a window of 2 levels or less
+                                      is refused (the solve returns MCE_E_INVAL) */
 #define MCE_OPT_SPLIT_THRESHOLD 4  /* hand over only frames whose P holds at least this many
                                       vertices (0 = auto) */
 #define MCE_OPT_CHECK_INTERVAL 5   /* children a wavefront examines between two looks at its

@@ -354,7 +354,13 @@ struct mce_graph_s {
     DevBuf d_desc, d_in, d_adj, d_order;
     // workspace of the solve
     DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params, d_sub;
-    HostPinned h_params; // staging of the search parameters (stable for graph replays)
+    HostPinned h_params; // staging of the search parameters of direct (not replayed) solves
+    // parameter block of the captured graph: written once, before the capture,
+    // and read by every replay; no other solve touches it
+    DevBuf d_params_graph;
+    // bumped whenever a workspace buffer is reallocated: a captured graph holds
+    // the buffer addresses of its capture and is replayed only while they stand
+    uint64_t ws_gen = 0;
     HostPinned h_out; // results | ctl | hist, copied back in one go
     // chunk buffers of mce_enumerate_stream
     DevBuf d_sv, d_so;
@@ -365,6 +371,9 @@ struct mce_graph_s {
     } tune;
     hipGraphExec_t graph_exec = nullptr;
     LaunchCfg graph_cfg;
+    uint64_t graph_gen = 0;
+    // serving jobs submitted for this handle and not yet finished
+    uint32_t jobs_in_flight = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float prepare_ms = 0.f;
     bool prepared_timed = false;
@@ -442,6 +451,10 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         else c.wpb--;
     }
     c.lds_depth = depth;
+    // Sixteen wavefronts a workgroup with a stack window of two levels or
+    // less once ran past its time limit under an earlier work distribution,
+    // and no cause was shown; the shape is refused until one is.
+    if (c.wpb >= 16 && c.lds_depth <= 2) return MCE_E_INVAL;
     const uint32_t lds_bytes = search_lds_bytes(c.wave_lds_words, rec_words, c.wpb);
     if (o.blocks > 0) {
         c.blocks = (uint32_t)o.blocks;
@@ -474,7 +487,22 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     return MCE_OK;
 }
 
+int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c);
+
+// The workspace of a solve; a reallocated buffer makes any captured graph of
+// the handle stale (see ws_gen).
 int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
+{
+    const void* before[] = {h->d_results.p, h->d_hist.p, h->d_ctl.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
+                            h->d_spill.p, h->d_state.p, h->h_out.p};
+    const int rc = ensure_workspace_bufs(h, c);
+    const void* after[] = {h->d_results.p, h->d_hist.p, h->d_ctl.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
+                           h->d_spill.p, h->d_state.p, h->h_out.p};
+    if (std::memcmp(before, after, sizeof(before)) != 0) h->ws_gen++;
+    return rc;
+}
+
+int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c)
 {
     int rc;
     if ((rc = h->d_results.ensure(sizeof(DevResult) * h->num_graphs)) != MCE_OK) return rc;
@@ -533,8 +561,11 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
 }
 
 // The solve sequence on a stream: reset, root, search, copy-out.
+// d_sp: device copy of sp already written by the caller (a graph capture), or
+// null to stage sp through the handle's pinned block into d_params.
 int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, uint64_t first,
-                  uint64_t last, hipStream_t s, bool timed, const uint32_t* sub_bits = nullptr)
+                  uint64_t last, hipStream_t s, bool timed, const uint32_t* sub_bits = nullptr,
+                  const SearchParams* d_sp = nullptr)
 {
     HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.blocks, s));
     if (sub_bits) {
@@ -545,10 +576,13 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
         const uint32_t max_units = std::max<uint32_t>(1u, c.cap / h->num_graphs);
         HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, max_units, s));
     }
-    std::memcpy(h->h_params.p, &sp, sizeof(sp));
-    HIP_TRY(hipMemcpyAsync(h->d_params.p, h->h_params.p, sizeof(sp), hipMemcpyHostToDevice, s));
+    if (!d_sp) {
+        std::memcpy(h->h_params.p, &sp, sizeof(sp));
+        HIP_TRY(hipMemcpyAsync(h->d_params.p, h->h_params.p, sizeof(sp), hipMemcpyHostToDevice, s));
+        d_sp = h->d_params.as<SearchParams>();
+    }
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
-    HIP_TRY(launch_search(sp, h->d_params.as<SearchParams>(), h->max_w32, c.blocks, c.wpb, s));
+    HIP_TRY(launch_search(sp, d_sp, h->max_w32, c.blocks, c.wpb, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
     char* out = static_cast<char*>(h->h_out.p);
     HIP_TRY(hipMemcpyAsync(out, sp.results, sizeof(DevResult) * h->num_graphs, hipMemcpyDeviceToHost, s));
@@ -642,17 +676,25 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         (void)t0;
         HIP_TRY(hipEventRecord(g->ev[0], s));
         if (use_graph && !enumerate && first == 0 && last == UINT64_MAX) {
-            if (!g->graph_exec || !(g->graph_cfg == c)) {
+            // A captured graph is replayed only with the launch configuration
+            // and the workspace buffers it was captured with; its parameter
+            // block is its own (the solves outside the graph stage theirs
+            // elsewhere), so a replay reads exactly what its capture wrote.
+            if (!g->graph_exec || !(g->graph_cfg == c) || g->graph_gen != g->ws_gen) {
                 if (g->graph_exec) {
                     (void)hipGraphExecDestroy(g->graph_exec);
                     g->graph_exec = nullptr;
                 }
+                if ((rc = g->d_params_graph.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
+                HIP_TRY(hipStreamSynchronize(s));
+                HIP_TRY(hipMemcpy(g->d_params_graph.p, &sp, sizeof(sp), hipMemcpyHostToDevice));
                 hipStream_t cs;
                 HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
                 hipGraph_t graph = nullptr;
                 hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    rc = enqueue_solve(g, c, sp, first, last, cs, false);
+                    rc = enqueue_solve(g, c, sp, first, last, cs, false, nullptr,
+                                       g->d_params_graph.as<SearchParams>());
                     e = hipStreamEndCapture(cs, &graph);
                 }
                 (void)hipStreamDestroy(cs);
@@ -667,6 +709,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
                     return hip_status(e);
                 }
                 g->graph_cfg = c;
+                g->graph_gen = g->ws_gen;
             }
             HIP_TRY(hipGraphLaunch(g->graph_exec, s));
         } else {
@@ -1297,7 +1340,11 @@ int mce_release(mce_graph_t g)
     if (!g) return MCE_OK;
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        (void)hipDeviceSynchronize();
+        // a served job still queued or running holds the handle
+        if (g->jobs_in_flight != 0) return MCE_E_BUSY;
+        // every solve waits for its own stream before it returns; only the
+        // prepare work (ordering, renumbering) may still be in flight
+        if (g->ev[1] && !g->prepared_timed) (void)hipEventSynchronize(g->ev[1]);
     }
     delete g;
     return MCE_OK;

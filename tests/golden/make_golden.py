@@ -8,7 +8,9 @@ repository root:
 Outputs (next to this script):
   full_configs.json   G(1000, 0.3) seed 0; Moon-Moser k = 15 and a relabelled
                       copy; planted G(800, 0.5) seed 0 (12 cliques of 20..40)
-  batch4096_seed0.csv the 4096-graph batch (base seed 0), one line per graph
+  batch4096_seed0.csv the 4096-graph batch (base seed 0), one line per graph;
+                      the hist column is the clique-size histogram without trailing
+                      zeros, entries separated by ";"
 """
 import argparse
 import json
@@ -50,12 +52,16 @@ def full_configs(threads):
 
 def batch(threads):
     specs = synth.batch_mix(4096, 0)
-    lines = ["index,n,p,seed,count,nodes,children,dead_ends,hash_xor,hash_sum,omega"]
+    lines = ["index,n,p,seed,count,nodes,children,dead_ends,hash_xor,hash_sum,omega,hist"]
     t0 = time.perf_counter()
     for i, (n, p, seed) in enumerate(specs):
         r = oracle.greedy(synth.gnp(n, p, seed), threads=threads)
-        lines.append("%d,%d,%r,%d,%d,%d,%d,%d,%d,%d,%d" % (i, n, p, seed, r["count"], r["nodes"], r["children"],
-                                                        r["dead_ends"], r["hash_xor"], r["hash_sum"], r["omega"]))
+        hist = list(r["hist"])
+        while len(hist) > 1 and hist[-1] == 0:
+            hist.pop()
+        lines.append("%d,%d,%r,%d,%d,%d,%d,%d,%d,%d,%d,%s" % (i, n, p, seed, r["count"], r["nodes"], r["children"],
+                                                           r["dead_ends"], r["hash_xor"], r["hash_sum"], r["omega"],
+                                                           ";".join(str(x) for x in hist)))
     print("batch", len(specs), round(time.perf_counter() - t0, 1), "s", flush=True)
     return "\n".join(lines) + "\n"
 

@@ -86,9 +86,15 @@ def test_batch4096_full(mce):
         graphs.append(synth.gnp(n, p, seed))
     b = mce.Graph(batch=graphs)
     out = b.count()
-    bad = [i for i, (res, r) in enumerate(zip(out, ref)) if any(res[k] != int(r[k]) for k in KEYS)]
-    assert not bad, "graphs %s differ (first: %s vs %s)" % (bad[:10], out[bad[0]], ref[bad[0]])
     b.release()
+
+    def differs(res, r):
+        # every counter and the clique-size histogram (the golden lists it
+        # without trailing zeros)
+        return (any(res[k] != int(r[k]) for k in KEYS) or
+                list(res["hist"]) != [int(x) for x in r["hist"].split(";")])
+    bad = [i for i, (res, r) in enumerate(zip(out, ref)) if differs(res, r)]
+    assert not bad, "graphs %s differ (first: %s vs %s)" % (bad[:10], out[bad[0]], ref[bad[0]])
 
 
 def _sample_nodes(pos_adj, count, seed, cap=125, x_frac=0.1):

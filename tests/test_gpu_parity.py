@@ -80,6 +80,38 @@ def test_large_n_two_words_per_lane(mce, orc):
         g.release()
 
 
+def _with_top_clique(rows, k):
+    """rows plus a clique on the k highest input ids (their clique words sit in
+    the last lanes of the layout)."""
+    adj = synth.unpack_rows(rows)
+    n = adj.shape[0]
+    adj[n - k:, n - k:] = True
+    np.fill_diagonal(adj, False)
+    return synth.pack_rows(adj)
+
+
+# Lane-layout boundaries: w32 = ceil(n/32) = 63 (n = 1985..2016: one chunk,
+# the row's id word in lane 63, no slack after a frame), 64 (n = 2017..2048:
+# the first two-chunk layout, the id word in lane 0 of chunk 1), 127 (n = 4064:
+# the last two-chunk layout) and 128 (n = 4065: the first four-chunk layout).
+BOUNDARY = [(1985, 0.05, 31), (2016, 0.05, 32), (2017, 0.05, 33), (2048, 0.05, 34), (4064, 0.03, 35),
+            (4065, 0.03, 36)]
+
+
+@pytest.mark.parametrize("rule", ("greedy", "tomita_bb", "greedy_tx"))
+@pytest.mark.parametrize("n,p,seed", BOUNDARY)
+def test_lane_layout_boundaries(mce, orc, rule, n, p, seed):
+    rows = _with_top_clique(synth.gnp(n, p, seed), 24)
+    mce.set_option("pivot", mce.PIVOT_RULES[rule])
+    res, g = solve(mce, rows)
+    try:
+        assert list(g.order()) == list(orc.order(rows))
+        same(res, orc.greedy(rows, threads=8) if rule == "greedy" else orc.solve_rule(rows, rule))
+        assert res["omega"] >= 24
+    finally:
+        g.release()
+
+
 @pytest.mark.parametrize("n,p,seed", [(4097, 0.003, 4), (6000, 0.002, 5), (8161, 0.001, 6),
                                       (10000, 0.001, 7), (16384, 0.0005, 8)])
 def test_wide_rows(mce, orc, n, p, seed):
@@ -238,7 +270,8 @@ def test_batch_matches_single(mce, orc):
     {"check_interval": 2, "split_threshold": 1, "lds_depth": 1, "waves_per_block": 2},
     pytest.param({"waves_per_block": 16, "lds_depth": 2}, marks=pytest.mark.skip(
         reason="stalled past the test timeout once (16 wavefronts per workgroup, LDS depth 2, "
-               "spill-pool retry); cause not yet shown, kept off the GPU until it is")),
+               "spill-pool retry) under an earlier work distribution; cause not yet shown, so the "
+               "library refuses the shape (MCE_E_INVAL) and the case stays off the GPU")),
 ])
 def test_schedule_stress(mce, orc, opts):
     for k, v in opts.items():
@@ -248,6 +281,64 @@ def test_schedule_stress(mce, orc, opts):
         ref = orc.greedy(rows)
         res, g = solve(mce, rows)
         same(res, ref)
+        g.release()
+
+
+def test_graph_replay_after_other_solves(mce, orc):
+    """With the solve captured as a hipGraph for every count (graph = 2), a
+    count, an enumeration and a count on one handle: both counts equal the
+    oracle and the replayed count leaves the enumeration's buffers alone."""
+    import torch
+    mce.set_option("graph", 2)
+    rows = synth.gnp(150, 0.5, 12)
+    ref = orc.greedy(rows)
+    g = mce.Graph(rows)
+    try:
+        same(g.count(), ref)
+        res, verts, offs = g.enumerate()
+        same(res, ref)
+        torch.cuda.synchronize()
+        v0, o0 = verts.clone(), offs.clone()
+        same(g.count(), ref)
+        torch.cuda.synchronize()
+        assert torch.equal(verts, v0) and torch.equal(offs, o0)
+        # a range and a subproblem in between, then the replay again
+        nb = g.root_branches()
+        same(g.count_range(0, nb // 2), orc.greedy_range(rows, 0, nb // 2))
+        same(g.count(), ref)
+    finally:
+        g.release()
+
+
+def test_batch_graph_replay_after_autotune(mce, orc):
+    """A batch handle (its counts are replayed graphs by default): count,
+    autotune with a few trials (which resize the workspace), count."""
+    specs = synth.batch_mix(24, 5)
+    graphs = [synth.gnp(n, p, s) for n, p, s in specs]
+    refs = [orc.greedy(r) for r in graphs]
+    b = mce.Graph(batch=graphs)
+    try:
+        for r, ref in zip(b.count(), refs):
+            same(r, ref)
+        b.autotune(max_trials=3)
+        for r, ref in zip(b.count(), refs):
+            same(r, ref)
+        for r, ref in zip(b.count(), refs):
+            same(r, ref)
+    finally:
+        b.release()
+
+
+def test_refused_schedule_shape(mce):
+    # 16 wavefronts a workgroup with a stack window of two levels is refused
+    mce.set_option("waves_per_block", 16)
+    mce.set_option("lds_depth", 2)
+    g = mce.Graph(synth.gnp(60, 0.5, 1))
+    try:
+        with pytest.raises(mce.MceError) as e:
+            g.count()
+        assert e.value.code == mce.E_INVAL
+    finally:
         g.release()
 
 
@@ -275,7 +366,10 @@ def test_device_pointer_input(mce, orc):
 
 
 def test_serving_alone_equals_mix(mce, orc):
-    specs = synth.serving_mix(12, 3, n_hi=400)
+    # the serving mix's full range of sizes (n log-uniform in [64, 2048]),
+    # with its E[mu] <= 1e6 redraw
+    specs = synth.serving_mix(12, 3)
+    assert max(n for n, _, _ in specs) > 1024
     graphs = [synth.gnp(n, p, s) for n, p, s in specs]
     handles = [mce.Graph(r) for r in graphs]
     alone = [h.count() for h in handles]
@@ -284,7 +378,7 @@ def test_serving_alone_equals_mix(mce, orc):
         rc, res = mce.poll(t, r.shape[0], -1)
         assert rc == mce.OK
         same(res, a)
-        same(res, orc.greedy(r))
+        same(res, orc.greedy(r, threads=8))
     for h in handles:
         h.release()
 
