@@ -274,7 +274,8 @@ int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t *out, void *hip_
 /* Forget the tuned schedule of a handle (back to the automatic one). */
 int mce_clear_tuning(mce_graph_t g);
 
-/* Free the handle and its device memory.  NULL is accepted. */
+/* Free the handle and its device memory.  NULL is accepted.  MCE_E_BUSY if a
+ * job submitted with mce_submit for it has not finished. */
 int mce_release(mce_graph_t g);
 
 /* Static string for a status code. */

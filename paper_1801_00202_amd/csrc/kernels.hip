@@ -1997,12 +1997,14 @@ static hipError_t ensure_order_attr()
     return err;
 }
 
-hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
+hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n, uint64_t max_words,
                         const uint64_t* rows_in, uint32_t* order, hipStream_t s)
 {
     (void)hipGetLastError(); // report only this call's launch errors
-    // rows staged in LDS when the largest graph's fit in a workgroup's LDS
-    const uint64_t lds = (uint64_t)max_n * ((max_n + 63u) / 64u) * 8u;
+    // rows staged in LDS when the largest graph's (n rows of rw64 words, as
+    // given: a single graph's rows may be wider than ceil(n/64) words) fit in
+    // a workgroup's LDS
+    const uint64_t lds = max_words * 8u;
     int dev = 0, lds_max = 0;
     if (max_n <= 2048 && hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
@@ -2027,6 +2029,22 @@ hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t m
         hipLaunchKernelGGL(order_kernel<32>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
     else
         hipLaunchKernelGGL(order_kernel<64>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
+    return hipGetLastError();
+}
+
+// Fill count 32-bit words with value (a kernel, not a memset node: callers may
+// capture the stream).
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t count, uint32_t value)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t value, hipStream_t s)
+{
+    (void)hipGetLastError(); // report only this call's launch errors
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, count, value);
     return hipGetLastError();
 }
 

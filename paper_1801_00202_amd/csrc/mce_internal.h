@@ -162,8 +162,10 @@ inline uint32_t search_lds_bytes(uint32_t wave_lds_words, uint32_t rec_words, ui
 // Host-side launchers (kernels.hip).
 hipError_t launch_validate(const uint64_t* rows, uint32_t n, uint32_t rw, unsigned int* flag,
                            hipStream_t s);
-hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
+// max_words: the largest n * rw64 of the graphs (their input rows' words)
+hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n, uint64_t max_words,
                         const uint64_t* rows_in, uint32_t* order, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t value, hipStream_t s);
 hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
                           const uint64_t* rows_in, const uint32_t* order, uint32_t* adj,
                           hipStream_t s);

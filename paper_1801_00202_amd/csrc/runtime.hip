@@ -974,7 +974,9 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
         HIP_TRY(hipStreamSynchronize(s));
         if (bad) return MCE_E_INVAL;
     }
-    HIP_TRY(launch_order(h->d_desc.as<GraphDesc>(), h->num_graphs, h->max_n, h->d_in.as<uint64_t>(),
+    uint64_t max_words = 0;
+    for (const GraphDesc& gd : desc) max_words = std::max<uint64_t>(max_words, (uint64_t)gd.n * gd.rw64);
+    HIP_TRY(launch_order(h->d_desc.as<GraphDesc>(), h->num_graphs, h->max_n, max_words, h->d_in.as<uint64_t>(),
                          h->d_order.as<uint32_t>(), s));
     HIP_TRY(launch_relabel(h->d_desc.as<GraphDesc>(), h->num_graphs, h->max_n, h->d_in.as<uint64_t>(),
                            h->d_order.as<uint32_t>(), h->d_adj.as<uint32_t>(), s));
