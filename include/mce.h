@@ -274,6 +274,33 @@ int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t *out, void *hip_
 /* Forget the tuned schedule of a handle (back to the automatic one). */
 int mce_clear_tuning(mce_graph_t g);
 
+/*
+ * mce_count_noalloc -- for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mce_prepare + mce_count + mce_release of one graph in a single call that
+ * allocates nothing.  Every intermediate (ordering, renumbered rows, pool of
+ * root units, mailboxes, spill stack, totals) lives in a fixed device scratch
+ * area of MCE_NOALLOC_SCRATCH_BYTES that the library holds on each device it
+ * runs on until the process ends; a search whose stack outgrows the scratch
+ * runs again with fewer wavefronts, and fails with MCE_E_NOMEM only if not
+ * even one wavefront's stack fits.
+ *   n          vertices, 0 <= n <= MCE_NOALLOC_MAX_N
+ *   rows       DEVICE pointer to n rows of row_words uint64 words (format as
+ *              mce_prepare); read in place, validated on the device
+ *   res        as mce_count (hist/hist_len read from it, host memory)
+ *   hip_stream stream to run on (NULL: default); the call waits for it
+ * Results are those of mce_prepare + mce_count with the same options.  Calls
+ * on one device share its scratch area and are serialised by the library
+ * (the area keeps the last call's contents); two processes each have their
+ * own copy.
+ * Errors: MCE_E_INVAL (NULL, n > MCE_NOALLOC_MAX_N, short rows, non-simple
+ * graph), MCE_E_NOMEM, MCE_E_DEVICE.
+ */
+#define MCE_NOALLOC_MAX_N 2048u
+#define MCE_NOALLOC_SCRATCH_BYTES 33554432u /* 32 MiB */
+int mce_count_noalloc(uint32_t n, const uint64_t *rows, uint32_t row_words, mce_result_t *res,
+                      void *hip_stream);
+
 /* Free the handle and its device memory.  NULL is accepted.  MCE_E_BUSY if a
  * job submitted with mce_submit for it has not finished. */
 int mce_release(mce_graph_t g);

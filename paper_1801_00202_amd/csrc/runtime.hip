@@ -169,23 +169,35 @@ void pool_free(void* p, size_t sz)
     pl.cached += sz;
 }
 
-// Grow-only device buffer on the caching allocator.
+// Grow-only device buffer on the caching allocator, or a borrowed view of
+// fixed size (a slice of the allocation-free entry point's scratch area),
+// which is never reallocated or freed: asking it for more is MCE_E_NOMEM.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { reset(); }
+    void borrow(void* q, size_t n)
+    {
+        reset();
+        p = q;
+        bytes = n;
+        borrowed = true;
+    }
     void reset()
     {
-        pool_free(p, bytes);
+        if (!borrowed) pool_free(p, bytes);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     int ensure(size_t want)
     {
         if (want <= bytes && p) return MCE_OK;
+        if (borrowed) return MCE_E_NOMEM;
         reset();
         p = pool_alloc(want ? want : 8, &bytes);
         if (!p) {
@@ -256,19 +268,29 @@ void pinned_free(void* p, size_t sz)
 struct HostPinned {
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false; // a fixed host block owned elsewhere (not pinned)
     HostPinned() = default;
     HostPinned(const HostPinned&) = delete;
     HostPinned& operator=(const HostPinned&) = delete;
     ~HostPinned() { reset(); }
+    void borrow(void* q, size_t n)
+    {
+        reset();
+        p = q;
+        bytes = n;
+        borrowed = true;
+    }
     void reset()
     {
-        pinned_free(p, bytes);
+        if (!borrowed) pinned_free(p, bytes);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     int ensure(size_t want)
     {
         if (want <= bytes && p) return MCE_OK;
+        if (borrowed) return MCE_E_NOMEM;
         reset();
         p = pinned_alloc(want ? want : 8, &bytes);
         if (!p) {
@@ -374,6 +396,9 @@ struct mce_graph_s {
     uint64_t graph_gen = 0;
     // serving jobs submitted for this handle and not yet finished
     uint32_t jobs_in_flight = 0;
+    // workspace of fixed size (the allocation-free entry point): launch
+    // shapes are cut down to what it holds instead of growing it
+    bool fixed_ws = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float prepare_ms = 0.f;
     bool prepared_timed = false;
@@ -650,6 +675,42 @@ int ensure_events(mce_graph_s* h)
     return MCE_OK;
 }
 
+// Cut a launch configuration down to a workspace of fixed size: the pool of
+// root units, the mailboxes and wavefront states, and the spill pool.  A
+// rerun that needs a spill chunk for every wavefront (floor) runs with as
+// many wavefronts as chunks fit.  MCE_E_NOMEM if not even one chunk fits.
+int fit_fixed_workspace(mce_graph_s* h, LaunchCfg* c, uint32_t floor)
+{
+    const uint64_t rec_bytes = 4ull * (kRecHeader + 4ull * c->w32cap);
+    const uint64_t recs = h->d_rec.bytes / rec_bytes;
+    if (recs < 2) return MCE_E_NOMEM;
+    uint32_t cap = 1;
+    while (2ull * cap <= recs && 2ull * cap <= c->cap) cap *= 2;
+    c->cap = cap;
+    const uint64_t wg_max = std::min<uint64_t>(h->d_mail.bytes / sizeof(Mailbox), h->d_mail_rec.bytes / rec_bytes);
+    const uint64_t waves_max = h->d_state.bytes / 4;
+    const uint64_t chunk_bytes = 4ull * spill_frame_words(c->w32cap) * c->spill_levels;
+    const uint64_t chunks_fit = h->d_spill.bytes / chunk_bytes;
+    if (chunks_fit == 0 || wg_max == 0) return MCE_E_NOMEM;
+    uint64_t blocks = std::min<uint64_t>(c->blocks, wg_max);
+    uint32_t wpb = c->wpb;
+    while (blocks * wpb > waves_max) blocks--;
+    // every wavefront needs a chunk (a rerun after the pool ran out)
+    if (floor != 0 && blocks * wpb > chunks_fit) {
+        if (chunks_fit >= wpb) {
+            blocks = chunks_fit / wpb;
+        } else {
+            blocks = 1;
+            wpb = (uint32_t)chunks_fit;
+        }
+    }
+    c->blocks = (uint32_t)std::max<uint64_t>(blocks, 1);
+    c->wpb = wpb;
+    const uint64_t waves = (uint64_t)c->blocks * c->wpb;
+    c->spill_chunks = (uint32_t)std::min<uint64_t>({(uint64_t)std::max(c->spill_chunks, std::min<uint32_t>(floor, (uint32_t)waves)), waves, chunks_fit});
+    return MCE_OK;
+}
+
 // Run one solve (count, count_range or enumerate) synchronously.
 int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, hipStream_t s,
               uint32_t* verts, uint64_t verts_cap, uint64_t* offs, uint64_t offs_cap,
@@ -662,6 +723,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
     for (int attempt = 0; attempt < 4; attempt++) {
         LaunchCfg c;
         if ((rc = make_cfg(g, &c, floor, blocks_cap, full_depth)) != MCE_OK) return rc;
+        if (g->fixed_ws && (rc = fit_fixed_workspace(g, &c, floor)) != MCE_OK) return rc;
         if ((rc = ensure_workspace(g, c)) != MCE_OK) return rc;
         SearchParams sp = make_params(g, c);
         const bool enumerate = verts != nullptr || offs != nullptr;
@@ -1353,6 +1415,145 @@ int mce_release(mce_graph_t g)
 }
 
 } // extern "C"
+
+// ------------------------------------------------- allocation-free entry --
+//
+// mce_count_noalloc runs the whole path of one graph (validation, ordering,
+// renumbering, root units, search, reduction) on buffers carved out of a
+// fixed device scratch area instead of allocated ones.  The area is the
+// file-scope device array below; each device the library runs on holds its
+// own copy until the process ends.  In host code the array's name is a
+// host-side stand-in, not a device address: its device address is taken
+// once per device (with that device current) by hipGetSymbolAddress, and only
+// that address is ever handed to kernels and copies.
+
+static __device__ __align__(256) unsigned char scratch[MCE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+// Fixed parts of the scratch area (the rest is the spill pool): a pool of
+// root units, mailboxes and record slots for up to kNoAllocWorkgroups search
+// workgroups, and states for up to kNoAllocWaves wavefronts.  Records are
+// sized for the widest layout the entry point takes (w32 = 64).
+constexpr uint32_t kNoAllocW32 = (MCE_NOALLOC_MAX_N + 31u) / 32u;
+constexpr uint32_t kNoAllocRecords = 8192, kNoAllocWorkgroups = 1024, kNoAllocWaves = 16384;
+
+struct NoAllocCtx {
+    std::mutex mu;
+    bool ready = false;
+    char* base = nullptr;          // device address of this device's scratch
+    mce_graph_s* h = nullptr;      // a handle whose buffers are views of the scratch
+    std::vector<unsigned char> host_out, host_params; // fixed host blocks
+};
+
+NoAllocCtx g_noalloc[kNoAllocDevices];
+
+// Set-up, once per device, with the device current: the scratch's device
+// address and the views of it.  The only allocations are host objects and
+// HIP events made here, before the first solve.
+int noalloc_setup(NoAllocCtx& x, int dev)
+{
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return MCE_E_DEVICE;
+    }
+    x.base = static_cast<char*>(ptr);
+    std::unique_ptr<mce_graph_s> h(new mce_graph_s());
+    h->device = dev;
+    h->num_graphs = 1;
+    h->desc.resize(1);
+    h->fixed_ws = true;
+    size_t off = 0;
+    auto take = [&](DevBuf& b, size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        b.borrow(x.base + off, bytes);
+        off += bytes;
+    };
+    const size_t rec_bytes = 4ull * (kRecHeader + 4ull * kNoAllocW32);
+    take(h->d_desc, sizeof(GraphDesc));
+    take(h->d_order, 4ull * MCE_NOALLOC_MAX_N);
+    take(h->d_adj, 4ull * ((uint64_t)MCE_NOALLOC_MAX_N * (kNoAllocW32 + 1) + 128));
+    take(h->d_results, sizeof(DevResult));
+    take(h->d_hist, 8ull * (MCE_NOALLOC_MAX_N + 1));
+    take(h->d_ctl, sizeof(QueueCtl));
+    take(h->d_params, sizeof(SearchParams));
+    take(h->d_sub, 256); // the validation flag
+    take(h->d_rec, rec_bytes * kNoAllocRecords);
+    take(h->d_mail, sizeof(Mailbox) * kNoAllocWorkgroups);
+    take(h->d_mail_rec, rec_bytes * kNoAllocWorkgroups);
+    take(h->d_state, 4ull * kNoAllocWaves);
+    if (off >= MCE_NOALLOC_SCRATCH_BYTES) return MCE_E_NOMEM;
+    h->d_spill.borrow(x.base + off, MCE_NOALLOC_SCRATCH_BYTES - off);
+    x.host_out.assign(sizeof(DevResult) + sizeof(QueueCtl) + 8ull * (MCE_NOALLOC_MAX_N + 1), 0);
+    x.host_params.assign(sizeof(SearchParams), 0);
+    h->h_out.borrow(x.host_out.data(), x.host_out.size());
+    h->h_params.borrow(x.host_params.data(), x.host_params.size());
+    int rc = ensure_events(h.get());
+    if (rc != MCE_OK) return rc;
+    x.h = h.release();
+    x.ready = true;
+    return MCE_OK;
+}
+
+} // namespace
+
+extern "C" int mce_count_noalloc(uint32_t n, const uint64_t* rows, uint32_t row_words, mce_result_t* res,
+                                 void* hip_stream)
+{
+    if (!res || n > MCE_NOALLOC_MAX_N) return MCE_E_INVAL;
+    if (n > 0 && (!rows || (uint64_t)row_words * 64u < n)) return MCE_E_INVAL;
+    if (n == 0) {
+        fill_empty_graph(0, UINT64_MAX, res);
+        return MCE_OK;
+    }
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc != MCE_OK) return rc;
+    if (di.device < 0 || di.device >= kNoAllocDevices) return MCE_E_DEVICE;
+    NoAllocCtx& x = g_noalloc[di.device];
+    std::lock_guard<std::mutex> lk(x.mu);
+    if (!x.ready && (rc = noalloc_setup(x, di.device)) != MCE_OK) return rc;
+    mce_graph_s* h = x.h;
+    std::lock_guard<std::mutex> hl(h->mu);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // this call's graph: the caller's rows are read in place
+    GraphDesc& gd = h->desc[0];
+    std::memset(&gd, 0, sizeof(gd));
+    gd.n = n;
+    gd.w32 = (n + 31) / 32;
+    gd.rstride = gd.w32 + 1;
+    gd.rw64 = row_words;
+    h->max_n = n;
+    h->max_w32 = gd.w32;
+    h->in_words = (uint64_t)n * row_words;
+    h->adj_words = (uint64_t)n * gd.rstride;
+    h->ord_words = n;
+    h->hist_total = n + 1;
+    h->tune = mce_graph_s::Tune();
+    h->spill_floor = 0;
+    h->spill_full_depth = false;
+    h->prepared_timed = false;
+    HIP_TRY(hipEventRecord(h->ev[0], s));
+    HIP_TRY(hipMemcpyAsync(h->d_desc.p, &gd, sizeof(GraphDesc), hipMemcpyHostToDevice, s));
+    // validation on the device (zero diagonal, symmetry, no padding bits)
+    unsigned int* flag = h->d_sub.as<unsigned int>();
+    HIP_TRY(launch_fill_u32(flag, 1, 0u, s));
+    HIP_TRY(launch_validate(rows, n, row_words, flag, s));
+    unsigned int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return MCE_E_INVAL;
+    HIP_TRY(launch_order(h->d_desc.as<GraphDesc>(), 1, n, (uint64_t)n * row_words, rows, h->d_order.as<uint32_t>(), s));
+    HIP_TRY(launch_relabel(h->d_desc.as<GraphDesc>(), 1, n, rows, h->d_order.as<uint32_t>(), h->d_adj.as<uint32_t>(), s));
+    HIP_TRY(hipEventRecord(h->ev[1], s));
+    if ((rc = finish_prepare_timing_locked(h)) != MCE_OK) return rc;
+    rc = run_solve(h, 0, UINT64_MAX, res, s, nullptr, 0, nullptr, 0, nullptr, false);
+    if (rc != MCE_OK) res->status = rc;
+    return rc;
+}
 
 // ------------------------------------------------------------ serving ----
 //

@@ -119,7 +119,7 @@ EXPORTS = (
     "mce_prepare", "mce_num_graphs", "mce_get_order", "mce_root_branches", "mce_count",
     "mce_count_range", "mce_count_subproblem", "mce_enumerate", "mce_submit", "mce_poll", "mce_cancel", "mce_release",
     "mce_strerror", "mce_set_option", "mce_get_option", "mce_last_stats", "mce_autotune", "mce_clear_tuning",
-    "mce_enumerate_stream",
+    "mce_enumerate_stream", "mce_count_noalloc",
 )
 
 # mce_clique_sink_t
@@ -167,6 +167,7 @@ def _lib():
         lib.mce_autotune.argtypes = [vp, u32, ctypes.POINTER(Tune), vp]
         lib.mce_clear_tuning.argtypes = [vp]
         lib.mce_enumerate_stream.argtypes = [vp, u64, SINK, vp, pres, vp]
+        lib.mce_count_noalloc.argtypes = [u32, vp, u32, pres, vp]
         for name in EXPORTS:
             if name != "mce_strerror":
                 getattr(lib, name).restype = i32
@@ -410,6 +411,26 @@ def cliques_from_output(verts, offsets, count: int):
     v = verts.cpu().numpy().astype(np.int64)
     o = offsets.cpu().numpy()[: 2 * count]
     return [tuple(int(x) for x in v[o[2 * i]:o[2 * i + 1]]) for i in range(count)]
+
+
+NOALLOC_MAX_N = 2048
+
+
+def count_noalloc(rows, stream=None) -> dict:
+    """mce_count_noalloc: the whole path of one graph given as a DEVICE
+    tensor [n, row_words] of 64-bit words, with no allocation in the
+    library."""
+    import torch
+    if not isinstance(rows, torch.Tensor) or not rows.is_cuda:
+        raise TypeError("count_noalloc takes the rows as a device tensor")
+    if rows.dtype not in (torch.int64, torch.uint64) or rows.dim() != 2:
+        raise ValueError("rows must be a 2-D 64-bit tensor [n, row_words]")
+    rows = rows.contiguous()
+    n, rw = rows.shape
+    r, h = _new_result(n)
+    _check(_lib().mce_count_noalloc(n, rows.data_ptr() if n else None, rw, ctypes.byref(r), _stream_ptr(stream)),
+           "mce_count_noalloc")
+    return _to_dict(r, h)
 
 
 def submit(graph: Graph, flags: int = 0) -> int:
