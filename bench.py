@@ -30,9 +30,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X peak of 32-bit integer vector lane operations: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz (bitwise integer ops have no packed form).
+# MI355X datasheet-derived peaks (the bench measures both on the box with the
+# probes of libmce_probe.so and uses the measured ones as denominators):
+# 32-bit integer vector lane operations, 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz (bitwise integer ops have no packed form); LDS reads, 256 bytes per
+# clock per CU (the probe measures about that on gfx950).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+LDS_PEAK_TBPS = 256 * 256 * 2.4e9 / 1e12
 # Paper, Table 1, GreedyBB at n=1000, p=0.3 (average of 10 graphs, one Xeon
 # E5-2690 v2 core): 15.487755M maximal cliques in 4.964 s.
 PAPER_G1000_CLIQUES_PER_S = 15.487755e6 / 4.964
@@ -57,6 +61,51 @@ def algorithmic_word_ops(res: dict, n: int) -> int:
     and two empty tests over W words."""
     w = (n + 31) // 32
     return w * (2 * res["nodes"] + 4 * res["children"])
+
+
+def algorithmic_lds_bytes(res: dict, n: int) -> int:
+    """LDS bytes the search's stack needs: a node's frame (P, X and L, one
+    32-bit word each per bitset word, plus the row kept for the next
+    candidate) written when it is pushed and read back when the search
+    returns to it."""
+    w = (n + 31) // 32
+    return 2 * 16 * w * res["nodes"]
+
+
+def measured_peaks() -> dict:
+    """int32 VALU lane-ops/s and LDS read bytes/s measured on this device by
+    the probes of libmce_probe.so (best of three launches each)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1801_00202_amd", "libmce_probe.so"))
+    d = ctypes.c_double
+    lib.mce_probe_valu.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(d), ctypes.POINTER(d)]
+    lib.mce_probe_lds.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(d), ctypes.POINTER(d)]
+    out = {}
+    for name, fn, blocks, iters in (("valu_lane_ops_per_s", lib.mce_probe_valu, 256 * 32, 4096),
+                                    ("lds_bytes_per_s", lib.mce_probe_lds, 256 * 32, 16384)):
+        best = 0.0
+        for _ in range(3):
+            rate, sec = d(), d()
+            rc = fn(blocks, iters, ctypes.byref(rate), ctypes.byref(sec))
+            if rc != 0:
+                raise RuntimeError("%s probe failed (%d)" % (name, rc))
+            best = max(best, rate.value)
+        out[name] = best
+    return out
+
+
+def cpu_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpu_logical_total": os.cpu_count(),
+            "cpu_affinity": len(os.sched_getaffinity(0))}
 
 
 def recorded_traffic(workload: str):
@@ -115,8 +164,10 @@ def batched(mce, synth, np, reps: int, tune: bool) -> dict:
     dt_plain = time.perf_counter() - t0
     for h in handles:
         h.release()
-    assert [r["hash_xor"] for r in plain] == [r["hash_xor"] for r in out]
+    assert plain == out, "batched and plain solves differ"
     return {"workload": "4096 graphs, n ~ U{32..512}, p ~ U[0.1,0.9], E[mu] <= 1e6, base seed 0",
+            "timed": "both sides time the solves of graphs prepared beforehand (ordering and renumbering "
+                     "excluded); the results of the two sides are compared in full (counters, hashes, histograms)",
             "autotune": None if tuned is None else {
                 k: tuned[k] for k in ("waves_per_block", "blocks", "lds_depth", "split_threshold",
                                       "check_interval", "trials")} | {
@@ -154,6 +205,7 @@ def table1_n10k(mce, synth, np, reps: int) -> dict:
             g.release()
             best = dt if best is None else min(best, dt)
         out["p=%g" % p] = {"ms": best * 1e3, "search_kernel_ms": st["search_kernel_us"] / 1e3,
+                           "prepare_ms": st["prepare_us"] / 1e3, "local_graphs": st["local_graphs"],
                            "cliques": res["count"], "nodes": res["nodes"], "omega": res["omega"],
                            "cliques_per_s": res["count"] / best,
                            "paper": {"cliques": mu, "steps": steps, "seconds": sec,
@@ -163,28 +215,41 @@ def table1_n10k(mce, synth, np, reps: int) -> dict:
 
 def serving(mce, synth, np, count: int, warm: int) -> dict:
     """Requests from the serving mix (n log-uniform in [64, 2048], p ~ U[0.2,
-    0.9], E[mu] <= 1e6), prepared on the device beforehand, submitted with
+    0.9], E[mu] <= 1e6; the redraw keeps n below about 950), submitted with
     mce_submit at Poisson arrival times; latency = completion - arrival on the
-    host monotonic clock.  Capacity = the closed-loop rate of the same mix;
-    open loop at 0.5 and 0.8 of it."""
+    host monotonic clock, measured two ways: with the request prepared at its
+    arrival (mce_prepare from host rows: validation, copy, ordering and
+    renumbering in the latency) and with every request prepared beforehand.
+    Capacity = the closed-loop rate of the same mix (all submitted at once);
+    plain = the same handles solved one after the other with mce_count; open
+    loop at 0.5 and 0.8 of the capacity."""
     specs = synth.serving_mix(count + warm, 11)
     graphs = [synth.gnp(n, p, seed) for n, p, seed in specs]
     handles = [mce.Graph(r) for r in graphs]
     ns = [r.shape[0] for r in graphs]
     for h in handles:              # every handle solved once: its workspace is allocated
         h.count()
+    # plain: one request after the other, each a blocking mce_count
+    t0 = time.perf_counter()
+    plain_cl = sum(h.count()["count"] for h in handles[warm:])
+    plain_wall = time.perf_counter() - t0
 
-    def run(arrivals):
+    def run(arrivals, prepare: bool):
         """arrivals: seconds from the start for requests warm..; returns
         (latencies, cliques, wall)."""
-        pending, lat, cliques = {}, [], 0
+        pending, lat, cliques, made = {}, [], 0, []
         nxt, t0 = 0, time.perf_counter()
         total = len(arrivals)
         while len(lat) < total:
             now = time.perf_counter() - t0
             while nxt < total and arrivals[nxt] <= now:
                 i = warm + nxt
-                pending[mce.submit(handles[i])] = (i, arrivals[nxt])
+                if prepare:
+                    g = mce.Graph(graphs[i])
+                    made.append(g)
+                else:
+                    g = handles[i]
+                pending[mce.submit(g)] = (i, arrivals[nxt])
                 nxt += 1
             for t in list(pending):
                 i, a = pending[t]
@@ -196,21 +261,101 @@ def serving(mce, synth, np, count: int, warm: int) -> dict:
                 lat.append(time.perf_counter() - t0 - a)
                 cliques += res["count"]
                 del pending[t]
-        return lat, cliques, time.perf_counter() - t0
+        wall = time.perf_counter() - t0
+        for g in made:
+            g.release()
+        return lat, cliques, wall
 
-    lat, cl, wall = run([0.0] * count)        # closed loop: everything at once
+    lat, cl, wall = run([0.0] * count, False)        # closed loop: everything at once
     capacity = count / wall
     result = {"workload": "serving mix, n log-uniform [64, 2048], p ~ U[0.2, 0.9], E[mu] <= 1e6, seed 11",
-              "requests": count, "capacity_rps": capacity, "capacity_cliques_per_s": cl / wall}
+              "requests": count, "max_n": max(ns), "capacity_rps": capacity, "capacity_cliques_per_s": cl / wall,
+              "plain_rps": count / plain_wall, "plain_cliques_per_s": plain_cl / plain_wall,
+              "served_vs_plain": plain_wall / wall,
+              "alone_share_pct": int(os.environ.get("MCE_SERVE_ALONE_PCT", "100"))}
     for frac in (0.5, 0.8):
-        arr = synth.poisson_arrivals(count, frac * capacity, 13)
-        lat, cl, wall = run(list(arr))
-        lat = np.array(lat) * 1e3
-        result["load_%g" % frac] = {"qps": frac * capacity, "p50_ms": float(np.percentile(lat, 50)),
-                                     "p99_ms": float(np.percentile(lat, 99)), "cliques_per_s": cl / wall}
+        arr = list(synth.poisson_arrivals(count, frac * capacity, 13))
+        for prep in (False, True):
+            lat, cl, wall = run(arr, prep)
+            lat = np.array(lat) * 1e3
+            result["load_%g%s" % (frac, "_with_prepare" if prep else "")] = {
+                "qps": frac * capacity, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "cliques_per_s": cl / wall}
     for h in handles:
         h.release()
     return result
+
+
+def config_legs(mce, synth, np, oracle_mod) -> dict:
+    """The other single-graph workloads, each as a whole job from device rows
+    (prepare + count + release), checked against expected results:
+    G(100, 0.5) seeds 0-9 (against the oracle, run here), planted G(800, 0.5)
+    and Moon-Moser k = 15 (against the committed oracle goldens and the
+    closed forms), and one node of G(300, 0.8) with about 10^8 cliques below
+    it (mce_count_subproblem, against its committed oracle golden; the whole
+    graph's 10^12 cliques are beyond any oracle run)."""
+    import torch
+    gold_dir = os.path.join(ROOT, "tests", "golden")
+    with open(os.path.join(gold_dir, "full_configs.json")) as f:
+        gold = json.load(f)
+    keys = ("count", "nodes", "children", "dead_ends", "hash_xor", "hash_sum", "omega")
+
+    def whole_job(rows, reps):
+        d = torch.from_numpy(rows.view(np.int64)).cuda()
+        torch.cuda.synchronize()
+        best, res = None, None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            g = mce.Graph(d)
+            res = g.count()
+            g.release()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return res, best
+
+    out = {}
+    # configs: G(100, 0.5), seeds 0-9
+    tot_cl, tot_nodes, tot_s, ok = 0, 0, 0.0, True
+    for seed in range(10):
+        rows = synth.gnp(100, 0.5, seed)
+        res, dt = whole_job(rows, 3)
+        ref = oracle_mod.greedy(rows)
+        ok = ok and all(res[k] == ref[k] for k in keys + ("hist",))
+        tot_cl += res["count"]
+        tot_nodes += res["nodes"]
+        tot_s += dt
+    out["gnp100_p0.5_seeds0-9"] = {"cliques": tot_cl, "nodes": tot_nodes, "ms_total": tot_s * 1e3,
+                                   "cliques_per_s": tot_cl / tot_s, "nodes_per_s": tot_nodes / tot_s,
+                                   "matches_oracle": ok}
+    for name, rows in (("moon_moser_15", synth.moon_moser(15)),
+                       ("planted800_p0.5_s0", synth.gnp_planted(800, 0.5, 0)[0])):
+        res, dt = whole_job(rows, 3 if name.startswith("moon") else 1)
+        ref = gold[name]
+        out[name] = {"cliques": res["count"], "nodes": res["nodes"], "ms": dt * 1e3,
+                     "cliques_per_s": res["count"] / dt, "nodes_per_s": res["nodes"] / dt,
+                     "matches_golden": all(res[k] == ref[k] for k in keys) and res["hist"] == ref["hist"],
+                     "golden_oracle_seconds": ref["oracle_seconds"], "golden_oracle_threads": ref["oracle_threads"]}
+    node_path = os.path.join(gold_dir, "gnp300_p0.8_node.json")
+    if os.path.exists(node_path):
+        with open(node_path) as f:
+            ref = json.load(f)
+        rows = synth.gnp(300, 0.8, 0)
+        g = mce.Graph(rows)
+        g.count_subproblem(ref["R"], ref["P"], ref["X"])          # warm-up
+        best, res = None, None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            res = g.count_subproblem(ref["R"], ref["P"], ref["X"])
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        g.release()
+        out["gnp300_p0.8_node"] = {
+            "node": {"R": len(ref["R"]), "P": len(ref["P"]), "X": len(ref["X"])},
+            "cliques": res["count"], "nodes": res["nodes"], "ms": best * 1e3,
+            "cliques_per_s": res["count"] / best, "nodes_per_s": res["nodes"] / best,
+            "matches_golden": all(res[k] == ref[k] for k in keys) and res["hist"] == ref["hist"],
+            "golden_oracle_seconds": ref["oracle_seconds"], "golden_oracle_threads": ref["oracle_threads"]}
+    return out
 
 
 def pivot_rules(mce, d_rows, reps: int) -> dict:
@@ -269,6 +414,9 @@ def main():
     ap.add_argument("--no-enumerate", action="store_true", help="skip the streamed enumeration")
     ap.add_argument("--no-table1", action="store_true", help="skip the n = 10^4 rows of Table 1")
     ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--no-configs", action="store_true", help="skip the other single-graph workloads")
+    ap.add_argument("--no-peaks", action="store_true", help="datasheet peaks instead of measured ones")
+    ap.add_argument("--only-serving", action="store_true", help="the serving leg alone (no headline line)")
     ap.add_argument("--no-tune", action="store_true", help="automatic schedule instead of mce_autotune's")
     ap.add_argument("--opts", default="", metavar="K=V,...",
                     help="fixed schedule (library options such as waves_per_block=8,blocks=512); no tuning")
@@ -290,6 +438,10 @@ def main():
     torch.cuda.set_device(0)
     mce.load()
     mce.reset_options(watchdog_ms=120000)
+    if args.only_serving:
+        print(json.dumps({"serving": serving(mce, synth, np, args.serving_requests, warm=100)}))
+        return
+    peaks = None if args.no_peaks else measured_peaks()
     wl = WORKLOADS[args.workload]
     rows = synth.gnp(wl["n"], wl["p"], wl["seed"])
     d_rows = torch.from_numpy(rows.view(np.int64)).cuda()
@@ -339,6 +491,10 @@ def main():
     k_us = sum(kernel_us) / len(kernel_us)
     ops = algorithmic_word_ops(first, wl["n"])
     achieved = ops / (k_us * 1e-6) / 1e12
+    lds_bytes = algorithmic_lds_bytes(first, wl["n"])
+    lds_achieved = lds_bytes / (k_us * 1e-6) / 1e12
+    valu_peak = VALU_PEAK_TOPS if peaks is None else peaks["valu_lane_ops_per_s"] / 1e12
+    lds_peak = LDS_PEAK_TBPS if peaks is None else peaks["lds_bytes_per_s"] / 1e12
     traffic = recorded_traffic(args.workload)
 
     line = {
@@ -372,10 +528,16 @@ def main():
         "autotune": None if tuned is None or "fixed" in tuned else {
             "trials": tuned["trials"], "auto_solve_ms": tuned["auto_us"] / 1e3, "tuned_solve_ms": tuned["best_us"] / 1e3},
         "schedule_fixed": None if tuned is None else tuned.get("fixed"),
-        "roofline": {"bound": "alu", "kernel": "search_kernel", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "T int32 lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
+        "roofline": {"bound": "alu", "kernel": "search_kernel", "achieved": achieved, "peak": valu_peak,
+                     "unit": "T int32 lane-ops/s", "frac": achieved / valu_peak,
+                     "peak_source": "datasheet" if peaks is None else "measured (libmce_probe valu probe)",
+                     "peak_datasheet": VALU_PEAK_TOPS,
                      "ops_per_launch": ops,
-                     "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"]},
+                     "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
+                     "lds": {"achieved": lds_achieved, "peak": lds_peak, "unit": "TB/s",
+                             "frac": lds_achieved / lds_peak, "bytes_per_launch": lds_bytes,
+                             "peak_source": "datasheet" if peaks is None else "measured (libmce_probe lds probe)",
+                             "peak_datasheet": LDS_PEAK_TBPS}},
     }
     mce.reset_options(watchdog_ms=120000)
     if not args.no_rules:
@@ -388,17 +550,31 @@ def main():
         line["batched"] = batched(mce, synth, np, reps=3, tune=not args.no_tune)
     if not args.no_serving:
         line["serving"] = serving(mce, synth, np, args.serving_requests, warm=100)
+    if not args.no_configs:
+        import oracle
+        line["configs"] = config_legs(mce, synth, np, oracle)
     if not args.no_cpu_baseline:
         import oracle
-        threads = args.cpu_threads or min(len(os.sched_getaffinity(0)), 16)
+        # all cores of the affinity mask over the whole workload graph (root
+        # children shared among threads), and one thread over the first 64 of
+        # the graph's root children
+        threads = args.cpu_threads or len(os.sched_getaffinity(0))
         c0 = time.perf_counter()
         ref = oracle.greedy(rows, threads=threads)
         cdt = time.perf_counter() - c0
         assert ref["count"] == first["count"] and ref["hash_xor"] == first["hash_xor"]
-        line["cpu_baseline"] = {"value": ref["count"] / cdt, "unit": "cliques/s", "cores": threads,
-                                "kind": "oracle", "seconds": cdt,
-                                "sample": "one full solve of the workload graph, root children shared "
-                                          "among the threads"}
+        c0 = time.perf_counter()
+        part = oracle.greedy_range(rows, 0, 64)
+        sdt = time.perf_counter() - c0
+        line["cpu_baseline"] = dict(cpu_info(), **{
+            "value": ref["count"] / cdt, "unit": "cliques/s", "cores": threads, "kind": "oracle",
+            "seconds": cdt,
+            "sample": "all-core: one full solve of the workload graph, root children shared among the threads; "
+                      "single-thread: root children 0..63 of the workload graph",
+            "single_thread": {"value": part["count"] / sdt, "unit": "cliques/s", "cores": 1, "seconds": sdt,
+                              "cliques": part["count"]}})
+    if peaks is not None:
+        line["measured_peaks"] = peaks
     print(json.dumps(line))
 
 

@@ -91,6 +91,11 @@ extern "C" {
                                         2 GreedyBBTX: a vertex of X maximising |P n N(p)|, else
                                           the first of P (GreedyBBNX picks the same pivot).
                                       Ties go to the earlier vertex of the ordering. */
+#define MCE_OPT_LOCAL_GRAPHS 11    /* single graphs of more than 4096 vertices: 1 (default) solves
+                                      each root child on the subgraph its neighbourhood induces
+                                      (same search tree, bitsets of |N(v)| + 1 bits) when every
+                                      root child has at most 2015 neighbours; 0 always uses
+                                      bitsets over all n vertices */
 
 typedef struct mce_graph_s *mce_graph_t; /* opaque; owns the device copy, order and rows */
 
@@ -228,10 +233,15 @@ int mce_enumerate_stream(mce_graph_t g, uint64_t chunk_verts, mce_clique_sink_t 
 
 /*
  * Serving.  mce_submit queues a count job for a prepared single-graph handle
- * and returns at once with a ticket.  Jobs run concurrently on the device as
- * capacity (HBM footprint and in-flight job slots) allows; a job that does not
- * fit waits in the host queue.  MCE_E_BUSY when the host queue is full.
- * The handle must stay alive until the job has been polled to completion.
+ * and returns at once with a ticket.  Up to four jobs run concurrently on the
+ * device; a queued job is admitted when its workspace fits the HBM budget
+ * (half the device memory free when serving starts) and its workgroups' LDS
+ * fits what the running jobs leave.  A job that starts alone gets the whole
+ * device (environment MCE_SERVE_ALONE_PCT, 1..100, sets a smaller share); one
+ * that starts while others run or wait gets an equal part of it, cut down to
+ * the LDS left, and waits while that is under an eighth of its width.
+ * MCE_E_BUSY when the host queue is full.  The handle must stay alive until
+ * the job has been polled (mce_release refuses it with MCE_E_BUSY before).
  */
 int mce_submit(mce_graph_t g, uint32_t flags, uint64_t *ticket);
 
@@ -241,8 +251,11 @@ int mce_submit(mce_graph_t g, uint32_t flags, uint64_t *ticket);
  * forgotten after it has returned anything but MCE_PENDING. */
 int mce_poll(uint64_t ticket, mce_result_t *res, int32_t timeout_us);
 
-/* Cancel a job that has not started on the device.  MCE_E_BUSY if it is
- * already running (it then completes normally), MCE_E_INVAL if unknown. */
+/* Cancel a job.  A queued job is dropped; a running one stops at the
+ * search's next look at its error bits (its workgroups read a word of
+ * coherent host memory that this call sets), and mce_poll then returns
+ * MCE_E_CANCELLED, or the results if it finished first.  MCE_E_BUSY if the
+ * job has already finished, MCE_E_INVAL if the ticket is unknown. */
 int mce_cancel(uint64_t ticket);
 
 /* mce_autotune -- choose this handle's launch schedule by timing it.
@@ -327,7 +340,7 @@ typedef struct {
     uint64_t checks;       /* times the search loop stopped to look at siblings and mailboxes */
     uint64_t flushes;      /* times it stopped to hash a full clique buffer */
     uint32_t attempts;     /* launches of the last call (a rerun follows an exhausted spill pool) */
-    uint32_t reserved;
+    uint32_t local_graphs; /* local graphs the search ran on (0: the whole graph's bitsets) */
     double busy_frac;      /* share of the search kernel's wavefront time spent on units */
     double ramp_frac;      /* share spent before a wavefront's first unit */
     double tail_frac;      /* share spent after its last unit (the rest of the idle time is

@@ -24,17 +24,28 @@ FLAGS = [
 ]
 
 
-def build(force: bool = True) -> str:
-    """Compile libmce.so (always, unless force is False and it is up to date)."""
-    if not force and os.path.exists(LIB):
-        newest = max(os.path.getmtime(p) for p in SOURCES + HEADERS)
-        if os.path.getmtime(LIB) >= newest:
-            return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *SOURCES]
+PROBE_LIB = os.path.join(PKG, "libmce_probe.so")
+PROBE_SOURCES = [os.path.join(PKG, "csrc", "probe.hip")]
+PROBE_HEADERS = [os.path.join(ROOT, "include", "mce_probe.h")]
+
+
+def _compile(lib: str, sources, headers, force: bool) -> str:
+    if not force and os.path.exists(lib):
+        newest = max(os.path.getmtime(p) for p in sources + headers)
+        if os.path.getmtime(lib) >= newest:
+            return lib
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *sources]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(force: bool = True) -> str:
+    """Compile libmce.so and the peak-rate probes libmce_probe.so (always,
+    unless force is False and they are up to date)."""
+    _compile(PROBE_LIB, PROBE_SOURCES, PROBE_HEADERS, force)
+    return _compile(LIB, SOURCES, HEADERS, force)
 
 
 if __name__ == "__main__":

@@ -260,6 +260,20 @@ __device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The launch's error bits, with a cancellation asked by the host folded in
+// when `look` (read from coherent host memory at system scope: a round trip
+// over the host link, so callers look only now and then).  Lane 0 only.
+__device__ __forceinline__ uint32_t error_or_cancel(const SearchParams& sp, bool look)
+{
+    uint32_t e = ld_dev(&sp.ctl->error);
+    if (e == 0u && look && sp.cancel &&
+        __hip_atomic_load(const_cast<uint32_t*>(sp.cancel), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+        atomicOr(&sp.ctl->error, kErrCancel);
+        e = kErrCancel;
+    }
+    return e;
+}
+
 // Wait until every vector memory access issued so far has completed.
 __device__ __forceinline__ void vm_drain()
 {
@@ -476,6 +490,211 @@ __global__ void __launch_bounds__(1024) order_wide_kernel(const GraphDesc* graph
     }
 }
 
+// Degree of every vertex (the popcount of its input row), one wavefront per
+// row, into deg (indexed like order): the first pass of the bucket ordering.
+__global__ void __launch_bounds__(256) degree_kernel(const GraphDesc* graphs, const uint64_t* rows_in, uint32_t* deg)
+{
+    const GraphDesc gd = graphs[blockIdx.y];
+    const uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (row >= gd.n) return;
+    const uint64_t* r = rows_in + gd.in_off + (uint64_t)row * gd.rw64;
+    uint32_t c = 0;
+    for (uint32_t w = lane_id(); w < gd.rw64; w += 64) c += (uint32_t)__builtin_popcountll(r[w]);
+    c = wave_sum(c);
+    if (lane_id() == 0) deg[gd.ord_off + row] = c;
+}
+
+// Maximum-degree-first ordering by degree buckets (Sec. 4.2), one workgroup
+// of 16 wavefronts per graph.  The vertices of the largest remaining degree d,
+// taken in increasing id, are exactly the next picks of the one-at-a-time rule
+// as long as each is adjacent to none of those picked before it in the same
+// round: picking a vertex lowers only its neighbours' degrees, so a bucket
+// member that is not a neighbour keeps degree d and is then the largest key
+// left (ties go to the smaller id); a member that is a neighbour drops below d
+// and waits for a later round.  So a round takes d = the largest degree and
+// scans the bucket in id order, and the number of rounds is far below n on
+// sparse graphs.  The scan goes by chunks of up to 64 members still at degree
+// d: all wavefronts copy the chunk's input rows to LDS (direct-to-LDS loads),
+// wavefront 0 works out which earlier chunk members each one is adjacent to (a
+// 64-bit mask) and the picks (a scalar scan of those masks), and all
+// wavefronts lower the degrees of the picks' neighbours (LDS atomics).  LDS:
+// the remaining degree + 1 of every vertex (0: taken), the round's bucket
+// (16-bit ids, up to kBucketCand), and the chunk's rows (KW x 64 words each,
+// plus one word of padding, so that lane j's row starts in bank j).  order
+// holds the degrees from degree_kernel on entry and the order on exit.
+constexpr uint32_t kBucketCand = 2048;
+
+struct BucketShared {
+    uint32_t red[16], red2[16];
+    uint32_t chk[64];   // the chunk: member ids
+    uint32_t cnum, cursor, pos, pad;
+    uint64_t pick;
+};
+// LDS the bucket kernels hold besides their dynamic part (BucketShared, rounded up)
+constexpr uint32_t kBucketStaticLds = 1024;
+static_assert(sizeof(BucketShared) <= kBucketStaticLds, "static LDS of the bucket kernels");
+
+template <int KW>
+__global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
+                                                            uint32_t* order, uint32_t ch)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ BucketShared sh;
+    const GraphDesc gd = graphs[blockIdx.x];
+    const uint32_t n = gd.n;
+    if (n == 0) return;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    constexpr uint32_t NWV = 16;
+    uint32_t* vw = lds;                                                      // n words
+    uint16_t* cand = reinterpret_cast<uint16_t*>(lds + ((n + 63u) & ~63u));  // kBucketCand
+    uint32_t* rowbuf = lds + ((n + 63u) & ~63u) + kBucketCand / 2;
+    constexpr uint32_t RS = KW * 64u + 1u; // LDS words between staged rows
+    uint32_t* ord = order + gd.ord_off;
+    const uint32_t* rw = reinterpret_cast<const uint32_t*>(rows_in + gd.in_off);
+    const uint32_t rs32 = 2u * gd.rw64; // 32-bit words of an input row
+    const uint32_t nw = (n + 31u) >> 5; // words that hold vertex bits
+    for (uint32_t v = t; v < n; v += 1024) vw[v] = ord[v] + 1u;
+    if (t == 0) sh.pos = 0;
+    __syncthreads();
+    // vertices of this thread for the per-round scans: [v0, v1) (an odd
+    // count a thread, so that a wavefront's words of a scan step sit in
+    // distinct LDS banks)
+    const uint32_t kpt = ((n + 1023u) >> 10) | 1u;
+    const uint32_t v0 = umin32(t * kpt, n), v1 = umin32(v0 + kpt, n);
+    for (;;) {
+        // the largest remaining degree + 1
+        uint32_t mx = 0;
+        for (uint32_t v = v0; v < v1; v++) mx = umax32(mx, vw[v]);
+        mx = wave_max(mx);
+        if (lane == 0) sh.red[wave] = mx;
+        __syncthreads();
+        mx = wave_max(lane < NWV ? sh.red[lane] : 0u);
+        if (mx == 0u) break;
+        // its bucket, in increasing id (threads hold consecutive id ranges)
+        uint32_t cnt = 0;
+        for (uint32_t v = v0; v < v1; v++) cnt += vw[v] == mx ? 1u : 0u;
+        const uint32_t incl = wave_scan_incl(cnt);
+        if (lane == 63) sh.red2[wave] = incl;
+        __syncthreads();
+        const uint32_t wtot = lane < NWV ? sh.red2[lane] : 0u;
+        const uint32_t wincl = wave_scan_incl(wtot);
+        const uint32_t total = rdlane(wincl, NWV - 1);
+        uint32_t k = rdlane(wincl - wtot, wave) + incl - cnt;
+        for (uint32_t v = v0; v < v1 && k < kBucketCand; v++)
+            if (vw[v] == mx) cand[k++] = (uint16_t)v;
+        const uint32_t T = umin32(total, kBucketCand);
+        if (t == 0) sh.cursor = 0;
+        __syncthreads();
+        for (;;) {
+            // the next chunk: up to 64 members still at the round's degree
+            if (wave == 0) {
+                uint32_t i = sh.cursor, cn = 0, mine = 0;
+                while (i < T && cn < 64u) {
+                    const uint32_t c = i + lane < T ? (uint32_t)cand[i + lane] : 0u;
+                    const bool live = i + lane < T && vw[c] == mx;
+                    const uint64_t lv = ballot(live);
+                    const uint32_t room = 64u - cn;
+                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(lv >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)lv, 0u));
+                    if (live && rk < room) sh.chk[cn + rk] = c;
+                    const uint32_t nl = (uint32_t)__builtin_popcountll(lv);
+                    if (nl <= room) {
+                        cn += nl;
+                        i += 64u;
+                    } else {
+                        // the chunk fills up inside this group: resume after its
+                        // last member taken
+                        uint64_t m = lv;
+                        for (uint32_t q = 0; q < room; q++) m &= m - 1ull;
+                        i += (uint32_t)__builtin_ctzll(m);
+                        cn = 64u;
+                    }
+                }
+                (void)mine;
+                if (lane == 0) {
+                    sh.cursor = i;
+                    sh.cnum = cn;
+                }
+            }
+            __syncthreads();
+            const uint32_t cnum = sh.cnum;
+            if (cnum == 0u) break;
+            // rows of the chunk into LDS: row j's words [64 q, 64 q + 64) by
+            // one load of a wavefront (words past the row's end read the
+            // row's first word and are never looked at); chunks of more than
+            // ch members take several passes
+            uint64_t pick = 0;
+            for (uint32_t base = 0; base < cnum; base += ch) {
+                const uint32_t pn = umin32(ch, cnum - base);
+                for (uint32_t j = wave; j < pn; j += NWV) {
+                    const uint32_t* src = rw + (size_t)sh.chk[base + j] * rs32;
+#pragma unroll
+                    for (int q = 0; q < KW; q++) {
+                        const uint32_t wi = (uint32_t)q * 64u + lane;
+                        __builtin_amdgcn_global_load_lds(src + (wi < rs32 ? wi : 0u),
+                                                         rowbuf + j * RS + (uint32_t)q * 64u, 4, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0): this wavefront's rows are in LDS
+                __syncthreads();
+                if (wave == 0) {
+                    // member j (in this pass): adjacent to which earlier chunk
+                    // members; then the picks, member by member
+                    const uint32_t jl = lane >= base && lane < base + pn ? lane - base : 0u;
+                    const uint32_t* myrow = rowbuf + jl * RS;
+                    const uint32_t cl = lane < cnum ? sh.chk[lane] : 0u;
+                    uint64_t conf = 0;
+                    for (uint32_t i = 0; i < base + pn; i++) {
+                        const uint32_t ci = rdlane(cl, i);
+                        const uint32_t bit = (myrow[ci >> 5] >> (ci & 31u)) & 1u;
+                        conf |= (i < lane && lane >= base && lane < base + pn && bit) ? (1ull << i) : 0ull;
+                    }
+                    for (uint32_t j = base; j < base + pn; j++) {
+                        const uint64_t cj = ((uint64_t)rdlane((uint32_t)(conf >> 32), j) << 32) |
+                                            rdlane((uint32_t)conf, j);
+                        if ((cj & pick) == 0ull) pick |= 1ull << j;
+                    }
+                    if (lane == 0) sh.pick = pick;
+                }
+                __syncthreads();
+                pick = sh.pick;
+                // the picks' neighbours lose one degree (picks are pairwise
+                // non-adjacent and no neighbour of an earlier pick, so none
+                // is touched)
+                for (uint32_t j = wave; j < pn; j += NWV) {
+                    if (!((pick >> (base + j)) & 1ull)) continue;
+                    const uint32_t* r = rowbuf + j * RS;
+#pragma unroll
+                    for (int q = 0; q < KW; q++) {
+                        const uint32_t wi = (uint32_t)q * 64u + lane;
+                        uint32_t bits = wi < nw ? r[wi] : 0u;
+                        while (bits) {
+                            const uint32_t u = (wi << 5) | (uint32_t)__builtin_ctz(bits);
+                            bits &= bits - 1u;
+                            if (vw[u] != 0u) atomicSub(&vw[u], 1u);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            // the picks, in member order, are the next entries of the order
+            if (wave == 0) {
+                const uint32_t cl = lane < cnum ? sh.chk[lane] : 0u;
+                const bool mine = (pick >> lane) & 1ull;
+                if (mine) {
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(pick >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)pick, 0u));
+                    ord[sh.pos + rank] = cl;
+                    vw[cl] = 0u;
+                }
+            }
+            __syncthreads();
+            if (t == 0) sh.pos += (uint32_t)__builtin_popcountll(pick);
+            __syncthreads();
+        }
+    }
+}
+
 // Renumbering (Sec. 4.2): row i of the new matrix is row order[i] of the input
 // with column j taken from column order[j].  Block (i, g), one word per thread.
 __global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
@@ -616,6 +835,46 @@ __global__ void __launch_bounds__(64) root_units_kernel(SearchParams sp, uint64_
     }
 }
 
+// The pivot of a node (P, X) of graph gd by the launch's pivot rule (Alg. 4
+// step 9; Sec. 4.3): GreedyBB, the first vertex of X if X is non-empty, else
+// the first of P; GreedyBBTX, the vertex of X maximising |P n N(u)| if X is
+// non-empty, else the first of P; TomitaBB, the vertex of P u X maximising
+// |P n N(u)|; ties to the earlier position.  -1 if P and X are empty.  One
+// wavefront.
+template <int WPL>
+__device__ int node_pivot(const SearchParams& sp, const GraphDesc& gd, const uint32_t (&P)[WPL],
+                          const uint32_t (&X)[WPL], uint32_t lane)
+{
+    const uint32_t W = gd.w32;
+    const uint32_t* adj = sp.adj + gd.adj_off;
+    int p = first_bit<WPL>(X);
+    if (sp.pivot_rule == kPivotTomita || (sp.pivot_rule == kPivotTX && p >= 0)) {
+        // the candidate maximising |P n N(u)|, the earliest on ties
+        uint32_t C[WPL];
+#pragma unroll
+        for (int c = 0; c < WPL; c++) C[c] = (sp.pivot_rule == kPivotTomita) ? (P[c] | X[c]) : X[c];
+        uint32_t bestc = 0;
+        p = -1;
+        for (int u = first_bit<WPL>(C); u >= 0; u = first_bit<WPL>(C)) {
+            clear_bit<WPL>(C, (uint32_t)u, lane);
+            const uint32_t* ru = adj + (size_t)(uint32_t)u * gd.rstride;
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t w = (uint32_t)c * 64u + lane;
+                cnt += (w < W) ? (uint32_t)__builtin_popcount(P[c] & ru[w]) : 0u;
+            }
+            cnt = wave_sum(cnt);
+            if (p < 0 || cnt > bestc) {
+                p = u;
+                bestc = cnt;
+            }
+        }
+    }
+    if (p < 0) p = first_bit<WPL>(P);
+    return p;
+}
+
 // One node (R, P, X) of graph 0, given as position bitsets (w32 words each,
 // R then P then X), as the only unit of the pool: R is mapped to input ids,
 // the node's pivot (by the launch's pivot rule) and L = P \ N(p) are taken
@@ -642,31 +901,7 @@ __global__ void __launch_bounds__(64) subproblem_kernel(SearchParams sp, const u
         clear_bit<WPL>(Rp, (uint32_t)q, lane);
         set_bit<WPL>(Rb, bcast0(ord[q]), lane);
     }
-    int p = first_bit<WPL>(X);
-    if (sp.pivot_rule == kPivotTomita || (sp.pivot_rule == kPivotTX && p >= 0)) {
-        // the candidate maximising |P n N(u)|, the earliest on ties
-        uint32_t C[WPL];
-#pragma unroll
-        for (int c = 0; c < WPL; c++) C[c] = (sp.pivot_rule == kPivotTomita) ? (P[c] | X[c]) : X[c];
-        uint32_t bestc = 0;
-        p = -1;
-        for (int u = first_bit<WPL>(C); u >= 0; u = first_bit<WPL>(C)) {
-            clear_bit<WPL>(C, (uint32_t)u, lane);
-            const uint32_t* ru = adj + (size_t)(uint32_t)u * gd.rstride;
-            uint32_t cnt = 0;
-#pragma unroll
-            for (int c = 0; c < WPL; c++) {
-                const uint32_t w = (uint32_t)c * 64u + lane;
-                cnt += (w < W) ? (uint32_t)__builtin_popcount(P[c] & ru[w]) : 0u;
-            }
-            cnt = wave_sum(cnt);
-            if (p < 0 || cnt > bestc) {
-                p = u;
-                bestc = cnt;
-            }
-        }
-    }
-    if (p < 0) p = first_bit<WPL>(P);
+    const int p = node_pivot<WPL>(sp, gd, P, X, lane);
     if (p < 0) return;
     const uint32_t* rp = adj + (size_t)(uint32_t)p * gd.rstride;
 #pragma unroll
@@ -688,6 +923,230 @@ __global__ void __launch_bounds__(64) subproblem_kernel(SearchParams sp, const u
         const uint32_t w = (uint32_t)c * 64u + lane;
         if (w < W) {
             rec[kRecHeader + w] = Rb[c];
+            rec[kRecHeader + cs + w] = P[c];
+            rec[kRecHeader + 2 * cs + w] = X[c];
+            rec[kRecHeader + 3 * cs + w] = L[c];
+        }
+    }
+}
+
+// ------------------------------------------------------- local graphs ----
+//
+// A sparse graph of more than 4096 vertices is solved root child by root
+// child, each on the subgraph induced by S = N(l) u {l} (Alg. 4 at the
+// root: the pivot is position 0, the children are L0 = {0} u (V \ N(0)) in
+// increasing position, and below child l every set the search forms lies in
+// N(l)).  S is numbered by increasing position, so the first vertex of a set
+// is the same vertex as in the whole graph and the search tree is the same
+// (same pivots, same branch orders, same node count); its members' ids are
+// ranked by increasing input id, so that a clique's local-id bitset lists it
+// in increasing input id, and a map turns the ranks back into input ids.
+// The local bitsets have ceil(|S| / 32) words instead of ceil(n / 32).
+
+// Per position v of the whole graph (renumbered rows, w32 words, stride
+// rstride): its degree, with bit 31 set if v is a root child (v = 0 or v not
+// adjacent to 0).  One wavefront per position.
+__global__ void __launch_bounds__(256) local_plan_kernel(const GraphDesc* gparent, const uint32_t* adj, uint32_t* out)
+{
+    const GraphDesc G = *gparent;
+    const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (v >= G.n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t* row = adj + G.adj_off + (size_t)v * G.rstride;
+    uint32_t c = 0;
+    for (uint32_t w = lane; w < G.w32; w += 64) c += (uint32_t)__builtin_popcount(row[w]);
+    c = wave_sum(c);
+    if (lane == 0) {
+        const uint32_t* row0 = adj + G.adj_off;
+        const bool root_child = v == 0u || ((row0[v >> 5] >> (v & 31u)) & 1u) == 0u;
+        out[v] = c | (root_child ? 0x80000000u : 0u);
+    }
+}
+
+// Exclusive prefix popcounts of words[0, W) into pref (one wavefront, eight
+// words a lane, W <= 512).
+__device__ __forceinline__ void word_prefix(const uint32_t* words, uint32_t* pref, uint32_t W, uint32_t lane)
+{
+    const uint32_t w0 = lane * 8u;
+    uint32_t loc[8], sum = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        loc[i] = (w0 + (uint32_t)i < W) ? (uint32_t)__builtin_popcount(words[w0 + i]) : 0u;
+        sum += loc[i];
+    }
+    uint32_t run = wave_scan_incl(sum) - sum;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        if (w0 + (uint32_t)i < W) pref[w0 + i] = run;
+        run += loc[i];
+    }
+}
+
+// Rank of bit b (< 32) of word w among the set bits of a bitset, given the
+// exclusive prefix popcounts of its words.
+__device__ __forceinline__ uint32_t bit_rank(const uint32_t* words, const uint32_t* pref, uint32_t w, uint32_t b)
+{
+    return pref[w] + (uint32_t)__builtin_popcount(words[w] & ((1u << b) - 1u));
+}
+
+// One workgroup of 256 per local graph (lgraphs[blockIdx.x]): its member
+// list, local order (local position -> local id), id map, rows (with the
+// local id after each row) and the P and X bitsets of the root child's node
+// (P = N(l) minus the earlier root children, X = N(l) and the earlier root
+// children), followed by the root child's own local id.
+__global__ void __launch_bounds__(256) local_build_kernel(const GraphDesc* gparent, const uint32_t* adj,
+                                                          const uint32_t* order, const GraphDesc* lgraphs,
+                                                          uint32_t* ladj, uint32_t* lord, uint32_t* lidmap,
+                                                          uint32_t* lpx)
+{
+    __shared__ uint32_t Sw[512], prefS[512], idw[512], prefI[512];
+    __shared__ uint32_t stage[4][64], pxw[2][64];
+    __shared__ uint16_t mem[kLocalMaxN];
+    const GraphDesc G = *gparent;
+    const GraphDesc L = lgraphs[blockIdx.x];
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    const uint32_t W = G.w32, p = L.rw64;
+    const uint32_t* grow = adj + G.adj_off;
+    const uint32_t* gord = order + G.ord_off;
+    // S = N(p) u {p}
+    for (uint32_t w = t; w < W; w += 256) {
+        Sw[w] = grow[(size_t)p * G.rstride + w] | (w == (p >> 5) ? (1u << (p & 31u)) : 0u);
+        idw[w] = 0u;
+    }
+    if (t < 128) pxw[t >> 6][t & 63u] = 0u;
+    __syncthreads();
+    if (wave == 0) word_prefix(Sw, prefS, W, lane);
+    // the members' input ids as a bitset over ids (ids are below n)
+    for (uint32_t w = t; w < W; w += 256) {
+        uint32_t bits = Sw[w];
+        while (bits) {
+            const uint32_t q = (w << 5) | (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1u;
+            const uint32_t id = gord[q];
+            atomicOr(&idw[id >> 5], 1u << (id & 31u));
+        }
+    }
+    __syncthreads();
+    if (wave == 0) word_prefix(idw, prefI, W, lane);
+    __syncthreads();
+    // local position a of member q, its local id, the map, the member list,
+    // and the node's P and X (q != p; X: a root child earlier than p)
+    const uint32_t* row0 = grow;
+    for (uint32_t w = t; w < W; w += 256) {
+        uint32_t bits = Sw[w];
+        while (bits) {
+            const uint32_t b = (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1u;
+            const uint32_t q = (w << 5) | b;
+            const uint32_t a = bit_rank(Sw, prefS, w, b);
+            const uint32_t id = gord[q];
+            const uint32_t lid = bit_rank(idw, prefI, id >> 5, id & 31u);
+            lord[L.ord_off + a] = lid;
+            lidmap[L.idmap_off + lid] = id;
+            mem[a] = (uint16_t)q;
+            if (q == p) {
+                lpx[L.in_off + 2u * L.w32] = lid;
+            } else {
+                const bool root_child = q == 0u || ((row0[q >> 5] >> (q & 31u)) & 1u) == 0u;
+                atomicOr(&pxw[(root_child && q < p) ? 1 : 0][a >> 5], 1u << (a & 31u));
+            }
+        }
+    }
+    __syncthreads();
+    if (t < L.w32) {
+        lpx[L.in_off + t] = pxw[0][t];
+        lpx[L.in_off + L.w32 + t] = pxw[1][t];
+    }
+    // rows: member a's row restricted to S, in local positions, then its id
+    for (uint32_t a = wave; a < L.n; a += 4) {
+        const uint32_t q = mem[a];
+        stage[wave][lane] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t* rq = grow + (size_t)q * G.rstride;
+        for (uint32_t w = lane; w < W; w += 64) {
+            uint32_t x = rq[w] & Sw[w];
+            while (x) {
+                const uint32_t b = (uint32_t)__builtin_ctz(x);
+                x &= x - 1u;
+                const uint32_t la = bit_rank(Sw, prefS, w, b);
+                atomicOr(&stage[wave][la >> 5], 1u << (la & 31u));
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint32_t* dst = ladj + L.adj_off + (size_t)a * L.rstride;
+        if (lane < L.w32) dst[lane] = stage[wave][lane];
+        if (lane == 0) {
+            const uint32_t id = gord[q];
+            dst[L.w32] = bit_rank(idw, prefI, id >> 5, id & 31u);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The root children of branch index [first, last) (local graph i is child i):
+// a child whose P is empty is a leaf, counted here (a maximal clique {l} if
+// X is also empty, else a dead end); any other becomes a node, counted, with
+// its pivot and L = P \ N(p), as a unit of the pool.  The root node counts
+// iff first == 0.  One wavefront per local graph.
+template <int WPL>
+__global__ void __launch_bounds__(64) local_units_kernel(SearchParams sp, const uint32_t* lpx, uint32_t count,
+                                                         uint64_t first, uint64_t last)
+{
+    const uint32_t i = blockIdx.x;
+    const uint32_t lane = lane_id();
+    DevResult* r = sp.results; // every local graph reports to result 0
+    if (i == 0 && first == 0 && last > 0 && lane == 0) atomicAdd(&r->nodes, 1ull);
+    if (i < first || i >= last || i >= count) return;
+    const GraphDesc gd = sp.graphs[i];
+    const uint32_t W = gd.w32, cs = sp.w32cap;
+    const uint32_t* px = lpx + gd.in_off;
+    uint32_t P[WPL], X[WPL], L[WPL];
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t w = (uint32_t)c * 64u + lane;
+        P[c] = w < W ? px[w] : 0u;
+        X[c] = w < W ? px[W + w] : 0u;
+    }
+    const uint32_t rootlid = px[2u * W];
+    if (lane == 0) atomicAdd(&r->children, 1ull);
+    if (!any_set<WPL>(P)) {
+        if (!any_set<WPL>(X) && lane == 0) {
+            // the clique {l}
+            const uint32_t id = sp.idmap[gd.idmap_off + rootlid];
+            const uint64_t h = mix64(mix64(1ull) + kGolden + (uint64_t)id);
+            atomicAdd(&r->count, 1ull);
+            atomicXor(&r->hash_xor, (unsigned long long)h);
+            atomicAdd(&r->hash_sum, (unsigned long long)h);
+            atomicMax(&r->omega, 1u);
+            atomicAdd(&sp.hist[gd.hist_off + 1], 1ull);
+        }
+        return;
+    }
+    const int p = node_pivot<WPL>(sp, gd, P, X, lane);
+    const uint32_t* rp = sp.adj + gd.adj_off + (size_t)(uint32_t)p * gd.rstride;
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t w = (uint32_t)c * 64u + lane;
+        L[c] = (w < W) ? (P[c] & ~rp[w]) : 0u;
+    }
+    uint32_t pos = 0;
+    if (lane == 0) {
+        atomicAdd(&r->nodes, 1ull);
+        pos = atomicAdd(&sp.ctl->pool_size, 1u);
+        atomicAdd(&sp.ctl->work, 1u);
+    }
+    pos = bcast0(pos);
+    uint32_t* rec = sp.rec + (size_t)pos * sp.rec_words;
+    if (lane == 0) rec[0] = i;
+#pragma unroll
+    for (int c = 0; c < WPL; c++) {
+        const uint32_t w = (uint32_t)c * 64u + lane;
+        if (w < W) {
+            rec[kRecHeader + w] = (w == (rootlid >> 5)) ? (1u << (rootlid & 31u)) : 0u; // R = {l}
             rec[kRecHeader + cs + w] = P[c];
             rec[kRecHeader + 2 * cs + w] = X[c];
             rec[kRecHeader + 3 * cs + w] = L[c];
@@ -816,9 +1275,14 @@ template <int WPL> struct LaneBits {
 // [start, start + cnt), with cent (lane i's saved word) = start << 16 | cnt.
 // Empties the buffer.  Off the hot path.
 __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restrict__ spp, uint32_t* wl,
-                                                     uint64_t hoff)
+                                                     uint32_t g_v)
 {
     const SearchParams& sp = *spp;
+    const GraphDesc& gd = sp.graphs[bcast0(g_v)];
+    const uint64_t hoff = gd.hist_off;
+    // a local graph reports its ids through its map (increasing: the order of
+    // a clique's ids is kept)
+    const uint32_t* idm = gd.idmap_off != kNoMap ? sp.idmap + gd.idmap_off : nullptr;
     const uint32_t lane = lane_id();
     const uint32_t nent = bcast0(wave_ctx(wl)->nent);
     const uint32_t cent = wl[kOffSave + 64 + lane];
@@ -840,7 +1304,8 @@ __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restr
             const uint32_t base = (e >> 16) << 4;
             uint32_t bits = e & 0xffffu;
             while (bits) {
-                h = mix64(h + kGolden + (uint64_t)(base + (uint32_t)__builtin_ctz(bits)));
+                const uint32_t id = base + (uint32_t)__builtin_ctz(bits);
+                h = mix64(h + kGolden + (uint64_t)(idm ? idm[id] : id));
                 bits &= bits - 1u;
             }
         }
@@ -896,7 +1361,8 @@ __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restr
                 const uint32_t base = (e >> 16) << 4;
                 uint32_t bits = e & 0xffffu;
                 while (bits) {
-                    sp.verts[q++] = base + (uint32_t)__builtin_ctz(bits);
+                    const uint32_t id = base + (uint32_t)__builtin_ctz(bits);
+                    sp.verts[q++] = idm ? idm[id] : id;
                     bits &= bits - 1u;
                 }
             }
@@ -918,7 +1384,7 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
     const uint64_t x = ctx->hx, s = ctx->hs;
     const uint64_t hoff = sp.graphs[g].hist_off;
     if (lane == 0) {
-        DevResult* r = sp.results + g;
+        DevResult* r = sp.results + sp.graphs[g].res;
         if (ctx->count) atomicAdd(&r->count, ctx->count);
         if (ctx->nodes) atomicAdd(&r->nodes, ctx->nodes);
         if (ctx->children) atomicAdd(&r->children, ctx->children);
@@ -1117,7 +1583,7 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                 }
             }
             rf = ++ctx->refreshes;
-            if ((rf & 7u) == 0u) e = ld_dev(&sp.ctl->error);
+            if ((rf & 7u) == 0u) e = error_or_cancel(sp, (rf & 63u) == 0u);
         }
         rf = bcast0(rf);
         const bool late = (rf & 63u) == 0u && sp.watchdog_ticks != 0 &&
@@ -1802,7 +2268,7 @@ __global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(Search
                     // (e) the end of the search, seen by a workgroup that holds no work
                     if (kind == 0 && inactive && (++polls % sp.poll_iters) == 0u) {
                         const uint32_t w = ld_dev(&sp.ctl->work);
-                        const uint32_t e = ld_dev(&sp.ctl->error);
+                        const uint32_t e = error_or_cancel(sp, (polls & 63u) == 0u);
                         const bool late = (polls & 63u) == 0u && overdue();
                         if (late) atomicOr(&sp.ctl->error, kErrWatchdog);
                         if (w == 0u || e != 0u || late) stop_now = 1;
@@ -1920,7 +2386,7 @@ __global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(Search
                 abort = bcast0(cold_check<WPL>(spp, smem, wl, W, g, t_start)) != 0u;
             } else if (why == kUnitFlush) {
                 if (lane == 0) ctx->flushes += 1;
-                cold_flush(spp, wl, sp.graphs[g].hist_off);
+                cold_flush(spp, wl, g);
             } else if (why == kUnitChunk) {
                 abort = bcast0(cold_spill_chunk(spp, wl)) == 0xffffffffu;
             } else {
@@ -1930,7 +2396,7 @@ __global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(Search
             }
             if (abort) break;
         }
-        if (bcast0(ctx->nent) != 0u) cold_flush(spp, wl, sp.graphs[g].hist_off);
+        if (bcast0(ctx->nent) != 0u) cold_flush(spp, wl, g);
         if (lane == 0) {
             const uint64_t t_end = wall_clock64();
             ctx->busy += t_end - t_unit;
@@ -1997,6 +2463,25 @@ static hipError_t ensure_order_attr()
     return err;
 }
 
+static hipError_t ensure_bucket_attr()
+{
+    // Allow the bucket ordering kernels the full LDS of a workgroup once per process.
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        int dev = 0, lds = 0;
+        err = hipGetDevice(&dev);
+        if (err == hipSuccess) err = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        // the kernels' static LDS (their shared scalars) comes on top
+        const void* ks[] = {(const void*)order_bucket_kernel<4>, (const void*)order_bucket_kernel<6>,
+                            (const void*)order_bucket_kernel<8>};
+        for (const void* k : ks)
+            if (err == hipSuccess)
+                err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds - (int)kBucketStaticLds);
+    });
+    return err;
+}
+
 hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n, uint64_t max_words,
                         const uint64_t* rows_in, uint32_t* order, hipStream_t s)
 {
@@ -2019,9 +2504,37 @@ hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t m
             hipLaunchKernelGGL(order_lds_kernel<32>, dim3(num_graphs), dim3(64), lds, s, graphs, rows_in, order);
         return hipGetLastError();
     }
-    if (max_n > 4096)
-        hipLaunchKernelGGL(order_wide_kernel, dim3(num_graphs), dim3(1024), 0, s, graphs, rows_in, order);
-    else if (max_n <= 512)
+    if (max_n > 4096) {
+        // degrees over the whole device, then the bucket rounds (one
+        // wavefront per graph) with as many staged rows per chunk as fit
+        const uint32_t kneed = (((max_n + 31u) / 32u) + 63u) / 64u; // words a lane of a row
+        const uint32_t kw = kneed <= 4u ? 4u : kneed <= 6u ? 6u : 8u;
+        const uint64_t fixed = 4ull * ((max_n + 63u) & ~63u) + 2ull * kBucketCand;
+        int dev = 0, lds_max = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return e;
+        const uint64_t row_bytes = 4ull * (kw * 64u + 1u);
+        const uint64_t stat = kBucketStaticLds;
+        uint64_t ch = ((uint64_t)lds_max > fixed + stat) ? ((uint64_t)lds_max - fixed - stat) / row_bytes : 0;
+        if (ch > 64) ch = 64;
+        if (ch < 8) {
+            hipLaunchKernelGGL(order_wide_kernel, dim3(num_graphs), dim3(1024), 0, s, graphs, rows_in, order);
+            return hipGetLastError();
+        }
+        const uint32_t lds = (uint32_t)(fixed + ch * row_bytes);
+        if ((e = ensure_bucket_attr()) != hipSuccess) return e;
+        hipLaunchKernelGGL(degree_kernel, dim3((max_n + 3u) / 4u, num_graphs), dim3(256), 0, s, graphs, rows_in, order);
+        if (kw == 4)
+            hipLaunchKernelGGL(order_bucket_kernel<4>, dim3(num_graphs), dim3(1024), lds, s, graphs, rows_in, order,
+                               (uint32_t)ch);
+        else if (kw == 6)
+            hipLaunchKernelGGL(order_bucket_kernel<6>, dim3(num_graphs), dim3(1024), lds, s, graphs, rows_in, order,
+                               (uint32_t)ch);
+        else
+            hipLaunchKernelGGL(order_bucket_kernel<8>, dim3(num_graphs), dim3(1024), lds, s, graphs, rows_in, order,
+                               (uint32_t)ch);
+    } else if (max_n <= 512)
         hipLaunchKernelGGL(order_kernel<8>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
     else if (max_n <= 1024)
         hipLaunchKernelGGL(order_kernel<16>, dim3(num_graphs), dim3(64), 0, s, graphs, rows_in, order);
@@ -2110,6 +2623,35 @@ hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uin
     case 4: hipLaunchKernelGGL(subproblem_kernel<4>, dim3(1), dim3(64), 0, s, sp, bits); break;
     default: hipLaunchKernelGGL(subproblem_kernel<8>, dim3(1), dim3(64), 0, s, sp, bits); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_local_plan(const GraphDesc* gparent, const uint32_t* adj, uint32_t n, uint32_t* out, hipStream_t s)
+{
+    (void)hipGetLastError(); // report only this call's launch errors
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(local_plan_kernel, dim3((n + 3u) / 4u), dim3(256), 0, s, gparent, adj, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_build(const GraphDesc* gparent, const uint32_t* adj, const uint32_t* order, uint32_t n,
+                              const GraphDesc* lgraphs, uint32_t count, uint32_t* ladj, uint32_t* lord,
+                              uint32_t* lidmap, uint32_t* lpx, hipStream_t s)
+{
+    (void)hipGetLastError(); // report only this call's launch errors
+    if (count == 0 || n > kMaxN) return n > kMaxN ? hipErrorInvalidValue : hipSuccess;
+    hipLaunchKernelGGL(local_build_kernel, dim3(count), dim3(256), 0, s, gparent, adj, order, lgraphs, ladj, lord,
+                       lidmap, lpx);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_units(const SearchParams& sp, const uint32_t* lpx, uint32_t count, uint32_t max_w32,
+                              uint64_t first, uint64_t last, hipStream_t s)
+{
+    (void)hipGetLastError(); // report only this call's launch errors
+    if (count == 0) return hipSuccess;
+    if (search_chunks(max_w32) != 1) return hipErrorInvalidValue; // local graphs have one-chunk layouts
+    hipLaunchKernelGGL(local_units_kernel<1>, dim3(count), dim3(64), 0, s, sp, lpx, count, first, last);
     return hipGetLastError();
 }
 

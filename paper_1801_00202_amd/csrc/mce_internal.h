@@ -67,7 +67,21 @@ struct GraphDesc {
     uint64_t adj_off;  // first uint32 word of the renumbered rows (row stride rstride)
     uint64_t ord_off;  // first entry of order[] (position -> input id)
     uint64_t hist_off; // first entry of the graph's histogram (n + 1 entries)
+    // Local graphs (the root children of a sparse graph of more than 4096
+    // vertices, each solved on the subgraph its neighbourhood induces): the
+    // ids of a local graph are local ranks, reported through idmap; an
+    // ordinary graph has idmap_off = kNoMap.
+    uint64_t idmap_off; // first entry of the id map (local id -> input id), or kNoMap
+    uint32_t res;       // the DevResult (and histogram) the graph's totals go to
+    uint32_t pad;
 };
+// For a local graph, rw64 holds the root child's position in the whole graph
+// and in_off the first word of its node's P and X bitsets (w32 words each,
+// local positions) followed by the root child's own local id, in lpx.
+constexpr uint64_t kNoMap = ~0ull;
+// Vertices of a local graph at most (one-chunk layout: w32 + 1 <= 64).
+constexpr uint32_t kLocalMaxN = 2016;
+static_assert(sizeof(GraphDesc) == 64, "GraphDesc layout");
 
 // Per-graph totals, accumulated with device atomics.
 struct DevResult {
@@ -112,6 +126,7 @@ constexpr unsigned int kMailNone = 0u, kMailUnit = 1u, kMailRefused = 2u;
 constexpr unsigned int kErrSpill = 1u; // spill pool exhausted: rerun with a larger pool
 constexpr unsigned int kErrDepth = 2u; // stack deeper than a spill chunk: rerun with chunks of full depth
 constexpr unsigned int kErrWatchdog = 4u; // the search ran past its deadline
+constexpr unsigned int kErrCancel = 16u;  // the host asked the search to stop (SearchParams.cancel)
 constexpr unsigned int kErrClique = 8u;   // a clique with more non-empty 16-bit id groups than the
                                           // clique buffer's slots (only possible for n > 8192)
 
@@ -146,6 +161,11 @@ struct SearchParams {
     uint32_t poll_iters;       // idle iterations between two looks at the end-of-search counter
     uint32_t* wave_state;     // per wavefront: kWave* phase (for deadline reports), or null
     uint32_t pivot_rule;      // kPivot*
+    uint32_t pad0;
+    // host-written word in coherent pinned host memory, or null: non-zero asks
+    // the search to stop (a served job cancelled while it runs)
+    const uint32_t* cancel;
+    const uint32_t* idmap;    // id maps of local graphs (GraphDesc.idmap_off), or null
 };
 // Pivot rules (SearchParams.pivot_rule, MCE_OPT_PIVOT).
 constexpr uint32_t kPivotGreedy = 0, kPivotTomita = 1, kPivotTX = 2;
@@ -174,6 +194,17 @@ hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hi
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
                        uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s);
 hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uint32_t* bits, hipStream_t s);
+// Local graphs of the root children of graph gparent (a single graph):
+// per position, its degree with bit 31 set when it is a root child; then the
+// local graphs themselves (rows, orders, id maps, the P and X bitsets of the
+// root child's node at lpx + in_off); then, per solve, the root children with
+// branch index in [first, last) as units (or leaves counted at once).
+hipError_t launch_local_plan(const GraphDesc* gparent, const uint32_t* adj, uint32_t n, uint32_t* out, hipStream_t s);
+hipError_t launch_local_build(const GraphDesc* gparent, const uint32_t* adj, const uint32_t* order, uint32_t n,
+                              const GraphDesc* lgraphs, uint32_t count, uint32_t* ladj, uint32_t* lord,
+                              uint32_t* lidmap, uint32_t* lpx, hipStream_t s);
+hipError_t launch_local_units(const SearchParams& sp, const uint32_t* lpx, uint32_t count, uint32_t max_w32,
+                              uint64_t first, uint64_t last, hipStream_t s);
 hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s);
 hipError_t search_occupancy(uint32_t max_w32, uint32_t rule, uint32_t waves_per_block, uint32_t lds_bytes,

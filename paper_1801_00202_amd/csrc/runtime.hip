@@ -38,6 +38,7 @@ struct Options {
     int64_t graph = 1;           // hipGraph replay: 0 never, 1 batches, 2 always
     int64_t refresh_children = 0; // 0: auto
     int64_t pivot = 0;            // kPivot*
+    int64_t local_graphs = 1;     // sparse graphs of more than 4096 vertices on local graphs: 0 never, 1 when they fit
 };
 
 std::mutex g_opt_mu;
@@ -394,11 +395,21 @@ struct mce_graph_s {
     hipGraphExec_t graph_exec = nullptr;
     LaunchCfg graph_cfg;
     uint64_t graph_gen = 0;
-    // serving jobs submitted for this handle and not yet finished
-    uint32_t jobs_in_flight = 0;
+    // serving jobs submitted for this handle and not yet finished, and
+    // whether one of them runs (jobs of one handle run one at a time: they
+    // share its workspace)
+    std::atomic<uint32_t> jobs_in_flight{0};
+    bool job_running = false; // guarded by the server's lock
     // workspace of fixed size (the allocation-free entry point): launch
     // shapes are cut down to what it holds instead of growing it
     bool fixed_ws = false;
+    // Local graphs of the root children (a single graph of more than 4096
+    // vertices whose root children all have at most kLocalMaxN - 1
+    // neighbours): built at the first solve that can use them and kept.
+    // local_state: 0 not looked at, 1 built, -1 not used for this handle.
+    int local_state = 0;
+    uint32_t lcount = 0, lmax_w32 = 0, lmax_n = 0;
+    DevBuf d_ldesc, d_ladj, d_lord, d_lidmap, d_lpx;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float prepare_ms = 0.f;
     bool prepared_timed = false;
@@ -428,19 +439,24 @@ constexpr uint32_t kSpillLevelsFirst = 64;
 // Bounds of the LDS stack window chosen when the caller sets none.
 constexpr uint32_t kAutoDepth = 12, kMinAutoDepth = 4;
 
+// local: the solve runs on the handle's local graphs (their widths, depths
+// and number of root units) instead of its own graphs.
 int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32_t blocks_cap = 0,
-             bool full_depth = false)
+             bool full_depth = false, bool local = false)
 {
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc != MCE_OK) return rc;
     const Options o = options();
+    const uint32_t mw32 = local ? h->lmax_w32 : h->max_w32;
+    const uint32_t mn = local ? h->lmax_n : h->max_n;
+    const uint64_t units = local ? h->lcount : h->num_graphs;
     LaunchCfg c;
     // an explicit option wins, then the handle's tuned choice, then the default
     c.wpb = o.waves_per_block > 0 ? (uint32_t)std::min<int64_t>(o.waves_per_block, 16)
                                   : (h->tune.wpb ? h->tune.wpb : 8u);
-    c.wpb = std::min<uint32_t>(c.wpb, max_search_wpb(search_chunks(h->max_w32)));
-    c.w32cap = std::max<uint32_t>(h->max_w32, 1u);
+    c.wpb = std::min<uint32_t>(c.wpb, max_search_wpb(search_chunks(mw32)));
+    c.w32cap = std::max<uint32_t>(mw32, 1u);
     c.rule = (uint32_t)o.pivot;
     c.slot_words = lds_frame_words(c.w32cap);
     const uint32_t slack = lds_slack_words(c.w32cap);
@@ -457,7 +473,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         // workgroups that the registers allow on a CU also fit in its LDS;
         // frames below it go to the spill pool.
         int by_regs = 0;
-        HIP_TRY(search_occupancy(h->max_w32, c.rule, c.wpb, 0, &by_regs));
+        HIP_TRY(search_occupancy(mw32, c.rule, c.wpb, 0, &by_regs));
         uint32_t wgs = (uint32_t)std::max(by_regs, 1);
         if (o.blocks <= 0 && h->tune.wgs_per_cu) wgs = std::min(wgs, h->tune.wgs_per_cu);
         depth = kAutoDepth;
@@ -485,7 +501,7 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
         c.blocks = (uint32_t)o.blocks;
     } else {
         int bpc = 0;
-        HIP_TRY(search_occupancy(h->max_w32, c.rule, c.wpb, lds_bytes, &bpc));
+        HIP_TRY(search_occupancy(mw32, c.rule, c.wpb, lds_bytes, &bpc));
         if (bpc < 1) bpc = 1;
         if (h->tune.wgs_per_cu) bpc = std::min<int>(bpc, (int)h->tune.wgs_per_cu);
         c.blocks = (uint32_t)di.cus * (uint32_t)bpc;
@@ -501,10 +517,10 @@ int make_cfg(mce_graph_s* h, LaunchCfg* cfg, uint32_t spill_chunks_floor, uint32
     c.check_interval = next_pow2(o.check_interval > 0 ? (uint64_t)o.check_interval
                                                       : (h->tune.check_interval ? h->tune.check_interval : ci_auto));
     uint64_t cap = o.queue_cap > 0 ? (uint64_t)o.queue_cap
-                                   : std::max<uint64_t>({(uint64_t)waves * 2u, (uint64_t)h->num_graphs * 2u, 1024u});
-    cap = std::max<uint64_t>(cap, (uint64_t)h->num_graphs + 1u);
+                                   : std::max<uint64_t>({(uint64_t)waves * 2u, units * 2u, 1024u});
+    cap = std::max<uint64_t>(cap, units + 1u);
     c.cap = next_pow2(cap);
-    c.spill_levels = h->max_n > c.lds_depth ? h->max_n - c.lds_depth : 1u;
+    c.spill_levels = mn > c.lds_depth ? mn - c.lds_depth : 1u;
     if (!full_depth) c.spill_levels = std::min(c.spill_levels, kSpillLevelsFirst);
     c.spill_chunks = std::max<uint32_t>(std::min<uint32_t>(waves, 64u), spill_chunks_floor);
     c.spill_chunks = std::min<uint32_t>(c.spill_chunks, waves);
@@ -546,13 +562,14 @@ int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c)
     return MCE_OK;
 }
 
-SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
+SearchParams make_params(mce_graph_s* h, const LaunchCfg& c, bool local = false)
 {
     SearchParams sp;
     std::memset(&sp, 0, sizeof(sp));
-    sp.graphs = h->d_desc.as<GraphDesc>();
-    sp.adj = h->d_adj.as<uint32_t>();
-    sp.order = h->d_order.as<uint32_t>();
+    sp.graphs = local ? h->d_ldesc.as<GraphDesc>() : h->d_desc.as<GraphDesc>();
+    sp.adj = local ? h->d_ladj.as<uint32_t>() : h->d_adj.as<uint32_t>();
+    sp.order = local ? h->d_lord.as<uint32_t>() : h->d_order.as<uint32_t>();
+    sp.idmap = local ? h->d_lidmap.as<uint32_t>() : nullptr;
     sp.results = h->d_results.as<DevResult>();
     sp.hist = h->d_hist.as<unsigned long long>();
     sp.ctl = h->d_ctl.as<QueueCtl>();
@@ -590,10 +607,13 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c)
 // null to stage sp through the handle's pinned block into d_params.
 int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, uint64_t first,
                   uint64_t last, hipStream_t s, bool timed, const uint32_t* sub_bits = nullptr,
-                  const SearchParams* d_sp = nullptr)
+                  const SearchParams* d_sp = nullptr, bool local = false)
 {
     HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.blocks, s));
-    if (sub_bits) {
+    if (local) {
+        // the root children [first, last) of the local graphs
+        HIP_TRY(launch_local_units(sp, h->d_lpx.as<uint32_t>(), h->lcount, h->lmax_w32, first, last, s));
+    } else if (sub_bits) {
         // one given node of graph 0 instead of the root
         HIP_TRY(launch_subproblem(sp, h->max_w32, sub_bits, s));
     } else {
@@ -607,7 +627,7 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
         d_sp = h->d_params.as<SearchParams>();
     }
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
-    HIP_TRY(launch_search(sp, d_sp, h->max_w32, c.blocks, c.wpb, s));
+    HIP_TRY(launch_search(sp, d_sp, local ? h->lmax_w32 : h->max_w32, c.blocks, c.wpb, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
     char* out = static_cast<char*>(h->h_out.p);
     HIP_TRY(hipMemcpyAsync(out, sp.results, sizeof(DevResult) * h->num_graphs, hipMemcpyDeviceToHost, s));
@@ -675,6 +695,69 @@ int ensure_events(mce_graph_s* h)
     return MCE_OK;
 }
 
+// The local graphs of a single graph of more than 4096 vertices, built once
+// (on stream s, which is then waited for): the degrees and root-child flags
+// of its positions come to the host, which lays the local graphs out (each
+// root child l: |N(l)| + 1 vertices) and gives up if one would be wider than
+// the one-chunk layout; the device then builds them.
+int ensure_local(mce_graph_s* h, hipStream_t s)
+{
+    if (h->local_state != 0) return MCE_OK;
+    h->local_state = -1;
+    if (h->fixed_ws || h->num_graphs != 1 || h->desc[0].n <= 4096u || options().local_graphs == 0) return MCE_OK;
+    const uint32_t n = h->desc[0].n;
+    DevBuf plan;
+    int rc;
+    if ((rc = plan.ensure(4ull * n)) != MCE_OK) return rc;
+    std::vector<uint32_t> hp(n);
+    HIP_TRY(launch_local_plan(h->d_desc.as<GraphDesc>(), h->d_adj.as<uint32_t>(), n, plan.as<uint32_t>(), s));
+    HIP_TRY(hipMemcpyAsync(hp.data(), plan.p, 4ull * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<GraphDesc> ld;
+    uint64_t adj = 0, ord = 0, px = 0;
+    uint32_t mw = 0, mn = 0;
+    for (uint32_t v = 0; v < n; v++) {
+        if (!(hp[v] & 0x80000000u)) continue;
+        const uint32_t k = (hp[v] & 0x7fffffffu) + 1u;
+        if (k > kLocalMaxN) return MCE_OK; // a wide neighbourhood: the whole graph's layout instead
+        GraphDesc gd;
+        std::memset(&gd, 0, sizeof(gd));
+        gd.n = k;
+        gd.w32 = (k + 31u) / 32u;
+        gd.rstride = gd.w32 + 1u;
+        gd.rw64 = v;     // the root child's position
+        gd.in_off = px;  // its node's P, X and own local id in lpx
+        gd.adj_off = adj;
+        gd.ord_off = ord;
+        gd.idmap_off = ord;
+        gd.hist_off = h->desc[0].hist_off;
+        gd.res = 0;
+        adj += (uint64_t)k * gd.rstride;
+        ord += k;
+        px += 2ull * gd.w32 + 1u;
+        mw = std::max(mw, gd.w32);
+        mn = std::max(mn, k);
+        ld.push_back(gd);
+    }
+    if (ld.empty()) return MCE_OK;
+    if ((rc = h->d_ldesc.ensure(sizeof(GraphDesc) * ld.size())) != MCE_OK) return rc;
+    // 128 words of padding: a row load reads up to 64 words from the row start
+    if ((rc = h->d_ladj.ensure(4 * (adj + 128))) != MCE_OK) return rc;
+    if ((rc = h->d_lord.ensure(4 * ord)) != MCE_OK) return rc;
+    if ((rc = h->d_lidmap.ensure(4 * ord)) != MCE_OK) return rc;
+    if ((rc = h->d_lpx.ensure(4 * px)) != MCE_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(h->d_ldesc.p, ld.data(), sizeof(GraphDesc) * ld.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_local_build(h->d_desc.as<GraphDesc>(), h->d_adj.as<uint32_t>(), h->d_order.as<uint32_t>(), n,
+                               h->d_ldesc.as<GraphDesc>(), (uint32_t)ld.size(), h->d_ladj.as<uint32_t>(),
+                               h->d_lord.as<uint32_t>(), h->d_lidmap.as<uint32_t>(), h->d_lpx.as<uint32_t>(), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->lcount = (uint32_t)ld.size();
+    h->lmax_w32 = mw;
+    h->lmax_n = mn;
+    h->local_state = 1;
+    return MCE_OK;
+}
+
 // Cut a launch configuration down to a workspace of fixed size: the pool of
 // root units, the mailboxes and wavefront states, and the spill pool.  A
 // rerun that needs a spill chunk for every wavefront (floor) runs with as
@@ -714,18 +797,26 @@ int fit_fixed_workspace(mce_graph_s* h, LaunchCfg* c, uint32_t floor)
 // Run one solve (count, count_range or enumerate) synchronously.
 int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, hipStream_t s,
               uint32_t* verts, uint64_t verts_cap, uint64_t* offs, uint64_t offs_cap,
-              QueueCtl* ctl_out, bool use_graph, uint32_t blocks_cap = 0, const uint32_t* sub_bits = nullptr)
+              QueueCtl* ctl_out, bool use_graph, uint32_t blocks_cap = 0, const uint32_t* sub_bits = nullptr,
+              const uint32_t* cancel = nullptr, uint32_t* lds_bytes_out = nullptr)
 {
     int rc = ensure_events(g);
     if (rc != MCE_OK) return rc;
+    // a whole-graph or root-range solve of a sparse wide graph runs on the
+    // local graphs of its root children
+    if (!sub_bits && (rc = ensure_local(g, s)) != MCE_OK) return rc;
+    const bool local = !sub_bits && g->local_state == 1;
+    if (local) use_graph = false;
     uint32_t floor = g->spill_floor;
     bool full_depth = g->spill_full_depth;
     for (int attempt = 0; attempt < 4; attempt++) {
         LaunchCfg c;
-        if ((rc = make_cfg(g, &c, floor, blocks_cap, full_depth)) != MCE_OK) return rc;
+        if ((rc = make_cfg(g, &c, floor, blocks_cap, full_depth, local)) != MCE_OK) return rc;
         if (g->fixed_ws && (rc = fit_fixed_workspace(g, &c, floor)) != MCE_OK) return rc;
         if ((rc = ensure_workspace(g, c)) != MCE_OK) return rc;
-        SearchParams sp = make_params(g, c);
+        SearchParams sp = make_params(g, c, local);
+        sp.cancel = cancel;
+        if (lds_bytes_out) *lds_bytes_out = search_lds_bytes(c.wave_lds_words, kRecHeader + 4 * c.w32cap, c.wpb) * c.blocks;
         const bool enumerate = verts != nullptr || offs != nullptr;
         if (enumerate) {
             sp.enumerate = 1;
@@ -775,7 +866,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
             }
             HIP_TRY(hipGraphLaunch(g->graph_exec, s));
         } else {
-            if ((rc = enqueue_solve(g, c, sp, first, last, s, true, sub_bits)) != MCE_OK) return rc;
+            if ((rc = enqueue_solve(g, c, sp, first, last, s, true, sub_bits, nullptr, local)) != MCE_OK) return rc;
         }
         HIP_TRY(hipEventRecord(g->ev[1], s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -801,6 +892,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
             g->spill_full_depth = full_depth;
             continue;
         }
+        if (ctl.error & kErrCancel) return MCE_E_CANCELLED;
         if (ctl.error & kErrClique) return MCE_E_NOMEM;
         if (ctl.error) return MCE_E_DEVICE;
         if (ctl_out) *ctl_out = ctl;
@@ -810,6 +902,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         if (hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess) st.search_us = ms * 1000.0;
         // a replayed graph carries no events around the search kernel
         const bool replayed = use_graph && !enumerate && first == 0 && last == UINT64_MAX;
+        st.local_graphs = local ? g->lcount : 0;
         if (!replayed && hipEventElapsedTime(&ms, g->ev[2], g->ev[3]) == hipSuccess)
             st.search_kernel_us = ms * 1000.0;
         (void)hipGetLastError(); // a failed timing query must not surface in a later launch check
@@ -908,6 +1001,10 @@ int mce_set_option(int key, int64_t value)
         if (value < 0 || value > 2) return MCE_E_INVAL;
         g_opt.pivot = value;
         return MCE_OK;
+    case MCE_OPT_LOCAL_GRAPHS:
+        if (value < 0 || value > 1) return MCE_E_INVAL;
+        g_opt.local_graphs = value;
+        return MCE_OK;
     default: return MCE_E_INVAL;
     }
 }
@@ -927,6 +1024,7 @@ int mce_get_option(int key, int64_t* value)
     case MCE_OPT_GRAPH: *value = g_opt.graph; return MCE_OK;
     case MCE_OPT_REFRESH_CHILDREN: *value = g_opt.refresh_children; return MCE_OK;
     case MCE_OPT_PIVOT: *value = g_opt.pivot; return MCE_OK;
+    case MCE_OPT_LOCAL_GRAPHS: *value = g_opt.local_graphs; return MCE_OK;
     default: return MCE_E_INVAL;
     }
 }
@@ -953,6 +1051,7 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
         if (n > 0 && (!rows || (uint64_t)row_words * 64u < n)) return MCE_E_INVAL;
         GraphDesc gd;
         std::memset(&gd, 0, sizeof(gd));
+        gd.idmap_off = kNoMap;
         gd.n = n;
         gd.w32 = (n + 31) / 32;
         gd.rstride = gd.w32 + 1;
@@ -973,6 +1072,8 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
             if (ni > MCE_MAX_N) return MCE_E_INVAL;
             GraphDesc gd;
             std::memset(&gd, 0, sizeof(gd));
+            gd.idmap_off = kNoMap;
+            gd.res = (uint32_t)i;
             gd.n = ni;
             gd.w32 = (ni + 31) / 32;
             gd.rstride = gd.w32 + 1;
@@ -1321,7 +1422,7 @@ int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t* out, void* hip_
     if ((rc = trial(best_t, &auto_us)) != MCE_OK) return rc;
     {
         LaunchCfg c;
-        if ((rc = make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth)) != MCE_OK) return rc;
+        if ((rc = make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth, g->local_state == 1)) != MCE_OK) return rc;
         DeviceInfo di;
         if ((rc = device_info(&di)) != MCE_OK) return rc;
         best_t.wpb = c.wpb;
@@ -1346,7 +1447,8 @@ int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t* out, void* hip_
     const mce_graph_s::Tune shape0 = best_t;
     for (uint32_t wpb : {4u, 8u, 16u}) {
         int by_regs = 0;
-        HIP_TRY(search_occupancy(g->max_w32, (uint32_t)options().pivot, wpb, 0, &by_regs));
+        HIP_TRY(search_occupancy(g->local_state == 1 ? g->lmax_w32 : g->max_w32, (uint32_t)options().pivot, wpb, 0,
+                             &by_regs));
         for (uint32_t k = 1; k <= (uint32_t)std::min(by_regs, 4); k++) {
             if (wpb == shape0.wpb && k == shape0.wgs_per_cu) continue;
             mce_graph_s::Tune t = shape0;
@@ -1354,7 +1456,8 @@ int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t* out, void* hip_
             t.wgs_per_cu = k;
             g->tune = t;
             LaunchCfg c;
-            if (make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth) != MCE_OK || c.lds_depth < 2 ||
+            if (make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth, g->local_state == 1) != MCE_OK ||
+                c.lds_depth < 2 ||
                 c.wpb != wpb)
                 continue; // too little LDS for a useful stack window
             if ((rc = consider(t)) != MCE_OK) return rc;
@@ -1378,7 +1481,7 @@ int mce_autotune(mce_graph_t g, uint32_t max_trials, mce_tune_t* out, void* hip_
     g->tune = best_t;
     if (out) {
         LaunchCfg c;
-        if ((rc = make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth)) != MCE_OK) return rc;
+        if ((rc = make_cfg(g, &c, g->spill_floor, 0, g->spill_full_depth, g->local_state == 1)) != MCE_OK) return rc;
         out->waves_per_block = c.wpb;
         out->blocks = c.blocks;
         out->lds_depth = c.lds_depth;
@@ -1402,10 +1505,12 @@ int mce_clear_tuning(mce_graph_t g)
 int mce_release(mce_graph_t g)
 {
     if (!g) return MCE_OK;
+    // a served job still queued or running holds the handle (checked before
+    // the handle's lock, which a running job holds)
+    if (g->jobs_in_flight.load() != 0) return MCE_E_BUSY;
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        // a served job still queued or running holds the handle
-        if (g->jobs_in_flight != 0) return MCE_E_BUSY;
+        if (g->jobs_in_flight.load() != 0) return MCE_E_BUSY;
         // every solve waits for its own stream before it returns; only the
         // prepare work (ordering, renumbering) may still be in flight
         if (g->ev[1] && !g->prepared_timed) (void)hipEventSynchronize(g->ev[1]);
@@ -1522,6 +1627,7 @@ extern "C" int mce_count_noalloc(uint32_t n, const uint64_t* rows, uint32_t row_
     // this call's graph: the caller's rows are read in place
     GraphDesc& gd = h->desc[0];
     std::memset(&gd, 0, sizeof(gd));
+    gd.idmap_off = kNoMap;
     gd.n = n;
     gd.w32 = (n + 31) / 32;
     gd.rstride = gd.w32 + 1;
@@ -1557,21 +1663,30 @@ extern "C" int mce_count_noalloc(uint32_t n, const uint64_t* rows, uint32_t row_
 
 // ------------------------------------------------------------ serving ----
 //
-// Jobs are admitted from a host FIFO into a fixed number of device slots as
-// slots and HBM free up.  Each slot owns a non-blocking stream and runs its
-// job's persistent search on a share of the device's workgroups, so jobs
-// that arrive while others run overlap with them on the device.
+// Jobs wait in a host FIFO and run on up to kSlots worker threads, each with a
+// stream of its own.  A job is admitted when its workspace fits the HBM
+// budget and its workgroups' LDS fits what the running jobs leave of the
+// device's LDS; its share of the device follows the load at admission: a job
+// that starts with nothing else running or waiting gets the share a lone job
+// is given (the whole device by default), one that starts while others run
+// or wait gets an equal part (at least 1 / kSlots), cut down to the LDS left.
+// A running job can be cancelled: its slot's word in coherent pinned host
+// memory is set, and the search stops at its next look at its error bits.
 
 namespace {
 
 struct Job {
     uint64_t ticket = 0;
     mce_graph_t g = nullptr;
-    int state = 0; // 0 queued, 1 running, 2 done, 3 cancelled
+    int state = 0; // 0 queued, 1 running, 2 done, 3 cancelled before it ran
     int status = MCE_OK;
+    uint32_t slot = 0;
     mce_result_t res;
     std::vector<uint64_t> hist;
-    uint64_t footprint = 0;
+    uint64_t hbm = 0;             // device memory of the job's workspace (all its workgroups)
+    uint32_t blocks_full = 0;     // workgroups of the job's solve on an idle device
+    uint64_t lds_per_block = 0;   // LDS bytes one of its workgroups holds
+    uint32_t blocks = 0;          // workgroups it was given
 };
 
 constexpr uint32_t kSlots = 4;
@@ -1585,7 +1700,11 @@ struct Server {
     std::vector<std::thread> workers;
     uint64_t next_ticket = 1;
     uint64_t hbm_budget = 0, hbm_used = 0;
-    uint32_t blocks_total = 0;
+    uint64_t lds_total = 0, lds_used = 0;
+    uint32_t running = 0;
+    uint32_t alone_pct = 100; // share of the device a job gets when it is alone
+    uint32_t wg_per_100v = 0; // at most this many workgroups per 100 vertices of the job's graph (0: no cap)
+    uint32_t* cancel = nullptr; // kSlots words, coherent pinned host memory
     bool started = false, stop = false;
     int device = -1;
     ~Server()
@@ -1606,15 +1725,48 @@ Server& server()
     return s;
 }
 
-// Device memory a job of this handle needs beyond what the handle holds.
-uint64_t job_footprint(mce_graph_s* h)
+// The job's demands on an idle device: workgroups, LDS per workgroup, and
+// device memory of its workspace.
+int job_demand(mce_graph_s* h, Job* job)
 {
     LaunchCfg c;
-    if (make_cfg(h, &c, 0) != MCE_OK) return 0;
+    int rc = make_cfg(h, &c, 0, 0, false, h->local_state == 1);
+    if (rc != MCE_OK) return rc;
     const uint64_t rec_words = kRecHeader + 4ull * c.w32cap;
-    return sizeof(DevResult) * h->num_graphs + 8ull * h->hist_total + 4ull * c.cap * rec_words +
-           (sizeof(Mailbox) + 4ull * rec_words) * c.blocks +
-           4ull * spill_frame_words(c.w32cap) * c.spill_levels * c.spill_chunks;
+    job->blocks_full = c.blocks;
+    job->lds_per_block = search_lds_bytes(c.wave_lds_words, (uint32_t)rec_words, c.wpb);
+    job->hbm = sizeof(DevResult) * h->num_graphs + 8ull * h->hist_total + 4ull * c.cap * rec_words +
+               (sizeof(Mailbox) + 4ull * rec_words) * c.blocks +
+               4ull * spill_frame_words(c.w32cap) * c.spill_levels * c.spill_chunks;
+    return MCE_OK;
+}
+
+// Workgroups for a queued job now (0: it does not fit yet).  Called with the
+// server lock held; waiting = queued jobs, this one included.
+uint32_t admit_blocks(const Server& sv, const Job& j, size_t waiting)
+{
+    if (sv.running != 0 && sv.hbm_used + j.hbm > sv.hbm_budget) return 0;
+    uint64_t full = std::max<uint32_t>(j.blocks_full, 1u);
+    // a small graph cannot keep many workgroups busy: each one only adds to
+    // the launch and to the end of the search
+    if (sv.wg_per_100v != 0)
+        full = std::min<uint64_t>(full, std::max<uint64_t>(16u, (uint64_t)j.g->desc[0].n * sv.wg_per_100v / 100u));
+    uint64_t want;
+    if (sv.running == 0 && waiting <= 1) {
+        want = std::max<uint64_t>(full * sv.alone_pct / 100, 1);
+    } else {
+        // as many jobs run at once as there are slots: each gets an equal part
+        want = std::max<uint64_t>(full / kSlots, 1);
+    }
+    const uint64_t lds_free = sv.lds_total > sv.lds_used ? sv.lds_total - sv.lds_used : 0;
+    const uint64_t fit = j.lds_per_block ? lds_free / j.lds_per_block : want;
+    // a job that would get less than an eighth of its own width waits for
+    // more room, unless nothing runs (then it takes what it asked for)
+    if (sv.running != 0) {
+        want = std::min(want, fit);
+        if (want < std::max<uint64_t>(full / 8, 1)) return 0;
+    }
+    return (uint32_t)want;
 }
 
 void worker_loop(uint32_t slot)
@@ -1629,43 +1781,54 @@ void worker_loop(uint32_t slot)
             std::unique_lock<std::mutex> lk(sv.mu);
             for (;;) {
                 if (sv.stop) break;
-                // first queued job that fits in the HBM budget (FIFO otherwise)
+                // drop entries cancelled before they ran
+                while (!sv.fifo.empty() && sv.fifo.front()->state == 3) sv.fifo.pop_front();
+                // the first queued job that fits (FIFO otherwise)
+                size_t waiting = 0;
+                for (auto& q : sv.fifo) waiting += q->state == 0;
                 for (auto it = sv.fifo.begin(); it != sv.fifo.end(); ++it) {
-                    if ((*it)->state != 0) continue;
-                    if (sv.hbm_used + (*it)->footprint <= sv.hbm_budget || sv.hbm_used == 0) {
+                    if ((*it)->state != 0 || (*it)->g->job_running) continue;
+                    const uint32_t b = admit_blocks(sv, **it, waiting);
+                    if (b != 0) {
                         job = *it;
+                        job->blocks = b;
                         sv.fifo.erase(it);
                         break;
                     }
                 }
-                // drop cancelled entries at the front
-                while (!sv.fifo.empty() && sv.fifo.front()->state == 3) sv.fifo.pop_front();
                 if (job) break;
                 sv.cv_work.wait(lk);
             }
             if (!job) break;
             job->state = 1;
-            sv.hbm_used += job->footprint;
+            job->slot = slot;
+            job->g->job_running = true;
+            sv.running++;
+            sv.hbm_used += job->hbm;
+            sv.lds_used += job->lds_per_block * job->blocks;
+            __atomic_store_n(&sv.cancel[slot], 0u, __ATOMIC_RELEASE);
         }
-        const uint32_t share = std::max<uint32_t>(sv.blocks_total / kSlots, 1u);
         int rc;
         {
             std::lock_guard<std::mutex> hl(job->g->mu);
             rc = finish_prepare_timing_locked(job->g);
             if (rc == MCE_OK)
                 rc = run_solve(job->g, 0, UINT64_MAX, &job->res, s, nullptr, 0, nullptr, 0, nullptr, false,
-                               share);
+                               job->blocks, nullptr, &sv.cancel[slot]);
         }
         {
             std::lock_guard<std::mutex> lk(sv.mu);
+            job->g->job_running = false;
+            job->g->jobs_in_flight.fetch_sub(1);
             job->status = rc;
             job->res.status = rc;
             job->state = 2;
-            sv.hbm_used -= job->footprint;
+            sv.running--;
+            sv.hbm_used -= job->hbm;
+            sv.lds_used -= job->lds_per_block * job->blocks;
         }
         sv.cv_done.notify_all();
         sv.cv_work.notify_all();
-        (void)slot;
     }
     if (s) (void)hipStreamDestroy(s);
 }
@@ -1679,11 +1842,28 @@ int server_start()
     if (rc != MCE_OK) return rc;
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    void* flags = nullptr;
+    HIP_TRY(hipHostMalloc(&flags, 4 * kSlots, hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(flags, 0, 4 * kSlots);
+    sv.cancel = static_cast<uint32_t*>(flags);
     sv.device = di.device;
     sv.hbm_budget = free_b / 2;
-    int bpc = 0;
-    HIP_TRY(search_occupancy(64, kPivotGreedy, 4, (kWaveFixedWords + 16 * 193) * 16, &bpc));
-    sv.blocks_total = (uint32_t)di.cus * (uint32_t)std::max(bpc, 1);
+    sv.lds_total = (uint64_t)di.cus * di.lds_per_cu;
+    if (const char* e = std::getenv("MCE_SERVE_ALONE_PCT")) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v >= 1 && v <= 100) sv.alone_pct = (uint32_t)v;
+    }
+    if (const char* e = std::getenv("MCE_SERVE_WG_PER_100V")) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v >= 0 && v <= 100000) sv.wg_per_100v = (uint32_t)v;
+    }
+    // the LDS the admitted jobs' workgroups may hold together, in percent of
+    // the device's (above 100: workgroups of later jobs queue in hardware
+    // for LDS that earlier jobs release)
+    if (const char* e = std::getenv("MCE_SERVE_LDS_PCT")) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v >= 10 && v <= 1000) sv.lds_total = sv.lds_total * (uint64_t)v / 100u;
+    }
     for (uint32_t i = 0; i < kSlots; i++) sv.workers.emplace_back(worker_loop, i);
     sv.started = true;
     return MCE_OK;
@@ -1705,7 +1885,8 @@ int mce_submit(mce_graph_t g, uint32_t flags, uint64_t* ticket)
     job->res.hist_len = (uint32_t)job->hist.size();
     {
         std::lock_guard<std::mutex> hl(g->mu);
-        job->footprint = job_footprint(g);
+        int rc = job_demand(g, job.get());
+        if (rc != MCE_OK) return rc;
     }
     {
         std::lock_guard<std::mutex> lk(sv.mu);
@@ -1713,6 +1894,7 @@ int mce_submit(mce_graph_t g, uint32_t flags, uint64_t* ticket)
         if (rc != MCE_OK) return rc;
         if (sv.fifo.size() >= kMaxQueued) return MCE_E_BUSY;
         job->ticket = sv.next_ticket++;
+        g->jobs_in_flight.fetch_add(1);
         sv.jobs[job->ticket] = job;
         sv.fifo.push_back(job);
         *ticket = job->ticket;
@@ -1734,6 +1916,8 @@ int mce_poll(uint64_t ticket, mce_result_t* res, int32_t timeout_us)
         if (timeout_us == 0) return MCE_PENDING;
         if (timeout_us < 0) sv.cv_done.wait(lk, done);
         else if (!sv.cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) return MCE_PENDING;
+        it = sv.jobs.find(ticket); // another thread may have polled it meanwhile
+        if (it == sv.jobs.end()) return MCE_E_INVAL;
     }
     sv.jobs.erase(it);
     if (job->state == 3) return MCE_E_CANCELLED;
@@ -1754,12 +1938,20 @@ int mce_cancel(uint64_t ticket)
     std::lock_guard<std::mutex> lk(sv.mu);
     auto it = sv.jobs.find(ticket);
     if (it == sv.jobs.end()) return MCE_E_INVAL;
-    if (it->second->state == 0) {
-        it->second->state = 3;
+    Job& j = *it->second;
+    if (j.state == 0) {
+        j.state = 3;
+        j.g->jobs_in_flight.fetch_sub(1);
         sv.cv_done.notify_all();
+        sv.cv_work.notify_all();
         return MCE_OK;
     }
-    return MCE_E_BUSY;
+    if (j.state == 1) {
+        // the search reads the word at its next look at its error bits
+        __atomic_store_n(&sv.cancel[j.slot], 1u, __ATOMIC_RELEASE);
+        return MCE_OK;
+    }
+    return MCE_E_BUSY; // finished (or cancelled) already
 }
 
 } // extern "C"

@@ -39,11 +39,12 @@ OPTIONS = {
     "graph": 8,
     "refresh_children": 9,
     "pivot": 10,
+    "local_graphs": 11,
 }
 DEFAULTS = {
     "waves_per_block": 0, "blocks": 0, "lds_depth": -1, "split_threshold": 0,
     "check_interval": 0, "queue_cap": 0, "watchdog_ms": 0, "graph": 1, "refresh_children": 0,
-    "pivot": 0,
+    "pivot": 0, "local_graphs": 1,
 }
 # values of the "pivot" option (MCE_OPT_PIVOT)
 PIVOT_RULES = {"greedy": 0, "tomita_bb": 1, "greedy_tx": 2}
@@ -95,7 +96,7 @@ class Stats(ctypes.Structure):
         ("checks", ctypes.c_uint64),
         ("flushes", ctypes.c_uint64),
         ("attempts", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("local_graphs", ctypes.c_uint32),
         ("busy_frac", ctypes.c_double),
         ("ramp_frac", ctypes.c_double),
         ("tail_frac", ctypes.c_double),

@@ -8,6 +8,8 @@ repository root:
 Outputs (next to this script):
   full_configs.json   G(1000, 0.3) seed 0; Moon-Moser k = 15 and a relabelled
                       copy; planted G(800, 0.5) seed 0 (12 cliques of 20..40)
+  gnp300_p0.8_node.json  one node of G(300, 0.8) seed 0 with about 10^8 maximal
+                      cliques below it (R, P, X as positions of the ordering)
   batch4096_seed0.csv the 4096-graph batch (base seed 0), one line per graph;
                       the hist column is the clique-size histogram without trailing
                       zeros, entries separated by ";"
@@ -50,6 +52,34 @@ def full_configs(threads):
     return out
 
 
+def gnp300_node(r_size=3, seed=17, x_frac=0.1):
+    """One node (R, P, X) of the search space of G(300, 0.8) seed 0, in the
+    positions of the maximum-degree-first ordering: R a clique of r_size
+    vertices grown from a seeded stream, C its common neighbourhood, X a
+    seeded tenth of C, P the rest.  The whole graph has about 10^12 maximal
+    cliques, beyond any oracle run; this node has about 10^8."""
+    rows = synth.gnp(300, 0.8, 0)
+    order = oracle.order(rows)
+    adj = synth.unpack_rows(rows)
+    pos = adj[np.ix_(order, order)]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R, C = [], np.ones(300, dtype=bool)
+    while len(R) < r_size:
+        v = int(rng.choice(np.flatnonzero(C)))
+        R.append(v)
+        C &= pos[v]
+        C[v] = False
+    cand = np.flatnonzero(C)
+    xm = rng.random(cand.size) < x_frac
+    P = [int(x) for x in cand[~xm]]
+    X = [int(x) for x in cand[xm]]
+    t0 = time.perf_counter()
+    r = oracle.subproblem(synth.pack_rows(pos), R, P, X, ids=order)
+    r.update({"R": R, "P": P, "X": X, "oracle_seconds": round(time.perf_counter() - t0, 2), "oracle_threads": 1})
+    print("gnp300 node", len(R), len(P), len(X), r["count"], r["nodes"], r["oracle_seconds"], flush=True)
+    return r
+
+
 def batch(threads):
     specs = synth.batch_mix(4096, 0)
     lines = ["index,n,p,seed,count,nodes,children,dead_ends,hash_xor,hash_sum,omega,hist"]
@@ -74,6 +104,9 @@ def main():
     if "full" in a.only:
         with open(os.path.join(HERE, "full_configs.json"), "w") as f:
             json.dump(full_configs(a.threads), f, indent=1, sort_keys=True)
+    if "gnp300node" in a.only:
+        with open(os.path.join(HERE, "gnp300_p0.8_node.json"), "w") as f:
+            json.dump(gnp300_node(), f, indent=1, sort_keys=True)
     if "batch" in a.only:
         with open(os.path.join(HERE, "batch4096_seed0.csv"), "w") as f:
             f.write(batch(a.threads))

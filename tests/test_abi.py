@@ -26,6 +26,24 @@ def _declared():
     return sorted(set(re.findall(r"\b(mce_[a-z_]+)\s*\(", src)))
 
 
+PROBE_HEADER = os.path.join(ROOT, "include", "mce_probe.h")
+
+
+def test_probe_library_exports_its_header():
+    # the peak-rate probes (a measurement aid beside libmce.so)
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1801_00202_amd", "libmce_probe.so"))
+    src = re.sub(r"/\*.*?\*/", "", open(PROBE_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(mce_probe_[a-z_]+)\s*\(", src)))
+    assert names == ["mce_probe_lds", "mce_probe_valu"]
+    for name in names:
+        assert hasattr(lib, name), name
+    d = ctypes.c_double()
+    # argument checks run before any HIP call
+    lib.mce_probe_valu.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.mce_probe_valu(0, 10, ctypes.byref(d), None) == -1
+    assert lib.mce_probe_valu(10, 10, None, None) == -1
+
+
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ("mce_prepare", "mce_count", "mce_enumerate", "mce_submit", "mce_poll",
@@ -156,8 +174,9 @@ def test_options(lib, mce):
         assert lib.mce_set_option(mce.OPTIONS["lds_depth"], -2) == mce.E_INVAL
         assert lib.mce_set_option(mce.OPTIONS["graph"], 3) == mce.E_INVAL
         assert lib.mce_set_option(mce.OPTIONS["pivot"], 3) == mce.E_INVAL
+        assert lib.mce_set_option(mce.OPTIONS["local_graphs"], 2) == mce.E_INVAL
         for name, key in mce.OPTIONS.items():
-            val = 2 if name in ("graph", "pivot") else 4
+            val = 2 if name in ("graph", "pivot") else 0 if name == "local_graphs" else 4
             assert lib.mce_set_option(key, val) == mce.OK
             assert lib.mce_get_option(key, ctypes.byref(v)) == mce.OK and v.value == val
     finally:

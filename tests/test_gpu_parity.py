@@ -124,6 +124,63 @@ def test_wide_rows(mce, orc, n, p, seed):
     g.release()
 
 
+def _hub(n, p, seed, hub, deg):
+    """G(n, p) with vertex `hub` joined to exactly `deg` vertices (a seeded
+    choice): the largest degree, so the hub is position 0 of the ordering and
+    the first root child, with `deg` neighbours."""
+    adj = synth.unpack_rows(synth.gnp(n, p, seed))
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    others = np.array([v for v in range(n) if v != hub])
+    pick = rng.choice(others, size=deg, replace=False)
+    adj[hub, :] = adj[:, hub] = False
+    adj[hub, pick] = adj[pick, hub] = True
+    return synth.pack_rows(adj)
+
+
+@pytest.mark.parametrize("rule", ("greedy", "tomita_bb", "greedy_tx"))
+def test_local_graphs(mce, orc, rule):
+    """Sparse graphs of more than 4096 vertices run root child by root child
+    on local graphs (bitsets over N(l) u {l}); the tree is the whole graph's,
+    so every counter equals the oracle's; with the option off, the whole
+    graph's layout gives the same.  The first root child's neighbourhood is
+    at the limit of the local layout (2015 neighbours: 2016 vertices,
+    w32 = 63) or one over it (then the whole graph's layout is used)."""
+    mce.set_option("pivot", mce.PIVOT_RULES[rule])
+    ref_fn = (lambda r: orc.greedy(r, threads=8)) if rule == "greedy" else (lambda r: orc.solve_rule(r, rule))
+    for rows, local in ((synth.gnp(7000, 0.002, 51), True), (_hub(5000, 0.001, 52, 17, 2015), True),
+                        (_hub(5000, 0.001, 53, 23, 2016), False)):
+        ref = ref_fn(rows)
+        for opt in (1, 0):
+            mce.set_option("local_graphs", opt)
+            res, g = solve(mce, rows)
+            try:
+                same(res, ref)
+                assert (mce.last_stats()["local_graphs"] > 0) == (local and opt == 1)
+            finally:
+                g.release()
+    mce.set_option("local_graphs", 1)
+
+
+def test_local_graph_ranges_and_lists(mce, orc):
+    """Root-child ranges and the streamed clique list on local graphs."""
+    rows = synth.gnp(5000, 0.004, 54)
+    g = mce.Graph(rows)
+    try:
+        nb = g.root_branches()
+        assert nb == orc.root_branches(rows)
+        for a, b in ((0, 1), (1, nb // 3), (nb // 3, nb)):
+            same(g.count_range(a, b), orc.greedy_range(rows, a, b))
+        ref, ref_list = orc.greedy_list(rows)
+        got = []
+        res = g.enumerate_stream(lambda verts, pairs: got.extend(
+            tuple(int(x) for x in verts[b:e]) for b, e in pairs), chunk_verts=50000)
+        same(res, ref)
+        assert sorted(got) == sorted(ref_list)
+        assert mce.last_stats()["local_graphs"] == nb
+    finally:
+        g.release()
+
+
 @pytest.mark.parametrize("rule", ("tomita_bb", "greedy_tx"))
 def test_wide_pivot_rules(mce, orc, rule):
     # the other pivot rules on the four- and eight-word layouts
@@ -398,6 +455,52 @@ def test_serving_alone_equals_mix(mce, orc):
         same(res, orc.greedy(r, threads=8))
     for h in handles:
         h.release()
+
+
+def test_serving_cancel_running_and_queued(mce):
+    """G(300, 0.8) has about 10^12 maximal cliques: its jobs run until they
+    are cancelled (the 20 s watchdog of these tests bounds them otherwise).
+    Whether a job is queued or running when it is cancelled, mce_poll
+    returns MCE_E_CANCELLED promptly.  A handle with a job in flight cannot be
+    released."""
+    import time
+    g = mce.Graph(synth.gnp(300, 0.8, 0))
+    try:
+        t1, t2, t3 = mce.submit(g), mce.submit(g), mce.submit(g)
+        time.sleep(0.3)
+        with pytest.raises(mce.MceError) as e:
+            g.release()
+        assert e.value.code == mce.E_BUSY
+        assert mce.poll(t1, 300, 0)[0] == mce.PENDING
+        assert mce.cancel(t3) == mce.OK
+        assert mce.poll(t3, 300, 10_000_000)[0] == mce.E_CANCELLED
+        t0 = time.perf_counter()
+        assert mce.cancel(t1) == mce.OK
+        assert mce.poll(t1, 300, 10_000_000)[0] == mce.E_CANCELLED
+        stop1 = time.perf_counter() - t0
+        time.sleep(0.2)
+        t0 = time.perf_counter()
+        assert mce.cancel(t2) == mce.OK
+        assert mce.poll(t2, 300, 10_000_000)[0] == mce.E_CANCELLED
+        stop2 = time.perf_counter() - t0
+        assert stop1 < 2.0 and stop2 < 2.0, (stop1, stop2)
+        assert mce.cancel(t1) == mce.E_INVAL  # forgotten once polled
+        # the handle still solves normally
+        nb = g.root_branches()
+        assert nb > 0
+    finally:
+        g.release()
+    # a job that finished before its cancellation keeps its result
+    rows = synth.gnp(60, 0.5, 3)
+    g = mce.Graph(rows)
+    try:
+        ref = g.count()
+        t = mce.submit(g)
+        rc, res = mce.poll(t, 60, -1)
+        assert rc == mce.OK
+        same(res, ref)
+    finally:
+        g.release()
 
 
 @pytest.mark.parametrize("n,p,seed", [(200, 0.5, 21), (120, 0.75, 22)])
