@@ -51,8 +51,14 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "search_kernel_gnp1000_traffic.
 
 
 def kernel_source_hash() -> str:
+    """sha256 (16 hex digits) of the search kernel's source: the part of
+    kernels.hip from the search section to the launchers (the other kernels
+    do not change what the search kernel's counters read)."""
     with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        src = f.read()
+    a = src.index(b"// ------------------------------------------------------ the search -------")
+    b = src.index(b"// ---------------------------------------------------------- launchers ----")
+    return hashlib.sha256(src[a:b]).hexdigest()[:16]
 
 
 def algorithmic_word_ops(res: dict, n: int) -> int:
@@ -272,7 +278,7 @@ def serving(mce, synth, np, count: int, warm: int) -> dict:
               "requests": count, "max_n": max(ns), "capacity_rps": capacity, "capacity_cliques_per_s": cl / wall,
               "plain_rps": count / plain_wall, "plain_cliques_per_s": plain_cl / plain_wall,
               "served_vs_plain": plain_wall / wall,
-              "alone_share_pct": int(os.environ.get("MCE_SERVE_ALONE_PCT", "100"))}
+              "alone_share_pct": int(os.environ.get("MCE_SERVE_ALONE_PCT", "50"))}
     for frac in (0.5, 0.8):
         arr = list(synth.poisson_arrivals(count, frac * capacity, 13))
         for prep in (False, True):

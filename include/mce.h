@@ -236,10 +236,12 @@ int mce_enumerate_stream(mce_graph_t g, uint64_t chunk_verts, mce_clique_sink_t 
  * and returns at once with a ticket.  Up to four jobs run concurrently on the
  * device; a queued job is admitted when its workspace fits the HBM budget
  * (half the device memory free when serving starts) and its workgroups' LDS
- * fits what the running jobs leave.  A job that starts alone gets the whole
- * device (environment MCE_SERVE_ALONE_PCT, 1..100, sets a smaller share); one
- * that starts while others run or wait gets an equal part of it, cut down to
- * the LDS left, and waits while that is under an eighth of its width.
+ * fits what the running jobs leave.  A job that starts alone spreads over
+ * every CU of the device with half of its full workgroup count, one
+ * workgroup per CU (environment MCE_SERVE_ALONE_PCT, 1..100, sets another
+ * share: the whole count, 100, measured slower on small graphs); one that
+ * starts while others run or wait gets a quarter, cut down to the LDS left,
+ * and waits while that is under an eighth of its width.
  * MCE_E_BUSY when the host queue is full.  The handle must stay alive until
  * the job has been polled (mce_release refuses it with MCE_E_BUSY before).
  */

@@ -643,11 +643,24 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
                     const uint32_t jl = lane >= base && lane < base + pn ? lane - base : 0u;
                     const uint32_t* myrow = rowbuf + jl * RS;
                     const uint32_t cl = lane < cnum ? sh.chk[lane] : 0u;
+                    // eight members a step, their words read before any is
+                    // looked at (the reads overlap instead of waiting in turn)
                     uint64_t conf = 0;
-                    for (uint32_t i = 0; i < base + pn; i++) {
-                        const uint32_t ci = rdlane(cl, i);
-                        const uint32_t bit = (myrow[ci >> 5] >> (ci & 31u)) & 1u;
-                        conf |= (i < lane && lane >= base && lane < base + pn && bit) ? (1ull << i) : 0ull;
+                    const uint32_t upto = base + pn;
+                    for (uint32_t i0 = 0; i0 < upto; i0 += 8) {
+                        uint32_t wv[8], ci[8];
+#pragma unroll
+                        for (int k = 0; k < 8; k++) {
+                            const uint32_t i = i0 + (uint32_t)k;
+                            ci[k] = rdlane(cl, i < upto ? i : 0u);
+                            wv[k] = myrow[ci[k] >> 5];
+                        }
+#pragma unroll
+                        for (int k = 0; k < 8; k++) {
+                            const uint32_t i = i0 + (uint32_t)k;
+                            const uint32_t bit = (wv[k] >> (ci[k] & 31u)) & 1u;
+                            conf |= (i < upto && i < lane && lane >= base && lane < upto && bit) ? (1ull << i) : 0ull;
+                        }
                     }
                     for (uint32_t j = base; j < base + pn; j++) {
                         const uint64_t cj = ((uint64_t)rdlane((uint32_t)(conf >> 32), j) << 32) |

@@ -1702,7 +1702,7 @@ struct Server {
     uint64_t hbm_budget = 0, hbm_used = 0;
     uint64_t lds_total = 0, lds_used = 0;
     uint32_t running = 0;
-    uint32_t alone_pct = 100; // share of the device a job gets when it is alone
+    uint32_t alone_pct = 50;  // share of the device's workgroups a job gets when it is alone
     uint32_t wg_per_100v = 0; // at most this many workgroups per 100 vertices of the job's graph (0: no cap)
     uint32_t* cancel = nullptr; // kSlots words, coherent pinned host memory
     bool started = false, stop = false;

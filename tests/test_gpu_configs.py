@@ -134,6 +134,19 @@ def test_gnp300_p08_sampled_nodes(mce, orc):
     g.release()
 
 
+def test_gnp300_p08_node_golden(mce):
+    """One depth-3 node of G(300, 0.8) with about 5.7e7 maximal cliques below
+    it, against the oracle's result stored by make_golden.py (its run takes
+    about 80 s on one core)."""
+    with open(os.path.join(GOLDEN, "gnp300_p0.8_node.json")) as f:
+        ref = json.load(f)
+    g = mce.Graph(synth.gnp(300, 0.8, 0))
+    try:
+        _same(g.count_subproblem(ref["R"], ref["P"], ref["X"]), ref)
+    finally:
+        g.release()
+
+
 def test_subproblem_at_root_is_whole_search(mce, orc):
     rows = synth.gnp(150, 0.5, 2)
     order = orc.order(rows)
