@@ -192,10 +192,14 @@ PAPER_N10K = {0.001: (50.006e3, 7.434e3, 0.034), 0.003: (142.630e3, 13.242e3, 0.
 
 
 def table1_n10k(mce, synth, np, reps: int) -> dict:
-    """The n = 10^4 rows of Table 1 (G(10^4, p), seed 0; eight 32-bit words a
-    lane): whole job per graph, from the device rows to the result (handle,
-    ordering, renumbering, search), best of reps."""
+    """The n = 10^4 rows of Table 1 (G(10^4, p), seed 0): whole job per graph,
+    from the device rows to the result (handle, ordering, renumbering, the
+    local graphs of the root children, search), best of reps; each result is
+    checked against the committed oracle golden."""
     import torch
+    with open(os.path.join(ROOT, "tests", "golden", "table1_n10k.json")) as f:
+        gold = json.load(f)
+    keys = ("count", "nodes", "children", "dead_ends", "hash_xor", "hash_sum", "omega", "hist")
     out = {}
     for p, (mu, steps, sec) in PAPER_N10K.items():
         rows = synth.gnp(10000, p, 0)
@@ -212,6 +216,7 @@ def table1_n10k(mce, synth, np, reps: int) -> dict:
             best = dt if best is None else min(best, dt)
         out["p=%g" % p] = {"ms": best * 1e3, "search_kernel_ms": st["search_kernel_us"] / 1e3,
                            "prepare_ms": st["prepare_us"] / 1e3, "local_graphs": st["local_graphs"],
+                           "matches_golden": all(res[k] == gold["p=%g" % p][k] for k in keys),
                            "cliques": res["count"], "nodes": res["nodes"], "omega": res["omega"],
                            "cliques_per_s": res["count"] / best,
                            "paper": {"cliques": mu, "steps": steps, "seconds": sec,

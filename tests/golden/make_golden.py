@@ -8,6 +8,7 @@ repository root:
 Outputs (next to this script):
   full_configs.json   G(1000, 0.3) seed 0; Moon-Moser k = 15 and a relabelled
                       copy; planted G(800, 0.5) seed 0 (12 cliques of 20..40)
+  table1_n10k.json    G(10^4, p) seed 0, p in {0.001, 0.003, 0.005, 0.01, 0.03}
   gnp300_p0.8_node.json  one node of G(300, 0.8) seed 0 with about 10^8 maximal
                       cliques below it (R, P, X as positions of the ordering)
   batch4096_seed0.csv the 4096-graph batch (base seed 0), one line per graph;
@@ -80,6 +81,19 @@ def gnp300_node(r_size=3, seed=17, x_frac=0.1):
     return r
 
 
+def table1_n10k(threads):
+    """G(10^4, p) seed 0 for the five p of Table 1's n = 10^4 rows."""
+    out = {}
+    for p in (0.001, 0.003, 0.005, 0.01, 0.03):
+        t0 = time.perf_counter()
+        r = oracle.greedy(synth.gnp(10000, p, 0), threads=threads)
+        r["oracle_seconds"] = round(time.perf_counter() - t0, 2)
+        r["oracle_threads"] = threads
+        out["p=%g" % p] = r
+        print("n=10^4 p=%g" % p, r["count"], r["nodes"], r["oracle_seconds"], flush=True)
+    return out
+
+
 def batch(threads):
     specs = synth.batch_mix(4096, 0)
     lines = ["index,n,p,seed,count,nodes,children,dead_ends,hash_xor,hash_sum,omega,hist"]
@@ -104,6 +118,9 @@ def main():
     if "full" in a.only:
         with open(os.path.join(HERE, "full_configs.json"), "w") as f:
             json.dump(full_configs(a.threads), f, indent=1, sort_keys=True)
+    if "table1" in a.only:
+        with open(os.path.join(HERE, "table1_n10k.json"), "w") as f:
+            json.dump(table1_n10k(a.threads), f, indent=1, sort_keys=True)
     if "gnp300node" in a.only:
         with open(os.path.join(HERE, "gnp300_p0.8_node.json"), "w") as f:
             json.dump(gnp300_node(), f, indent=1, sort_keys=True)

@@ -134,6 +134,25 @@ def test_gnp300_p08_sampled_nodes(mce, orc):
     g.release()
 
 
+@pytest.mark.parametrize("p", [0.001, 0.003, 0.005, 0.01, 0.03])
+def test_table1_n10k_rows(mce, p):
+    """The n = 10^4 rows of Table 1 (G(10^4, p) seed 0), whole graph on local
+    graphs, against the oracle's results stored by make_golden.py; with the
+    local graphs off, the whole graph's layout gives the same."""
+    with open(os.path.join(GOLDEN, "table1_n10k.json")) as f:
+        ref = json.load(f)["p=%g" % p]
+    rows = synth.gnp(10000, p, 0)
+    for local in (1, 0):
+        mce.set_option("local_graphs", local)
+        g = mce.Graph(rows)
+        try:
+            _same(g.count(), ref)
+            assert (mce.last_stats()["local_graphs"] > 0) == (local == 1)
+        finally:
+            g.release()
+    mce.set_option("local_graphs", 1)
+
+
 def test_gnp300_p08_node_golden(mce):
     """One depth-3 node of G(300, 0.8) with about 5.7e7 maximal cliques below
     it, against the oracle's result stored by make_golden.py (its run takes
