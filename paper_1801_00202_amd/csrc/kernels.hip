@@ -514,17 +514,24 @@ __global__ void __launch_bounds__(256) degree_kernel(const GraphDesc* graphs, co
 // and waits for a later round.  So a round takes d = the largest degree and
 // scans the bucket in id order, and the number of rounds is far below n on
 // sparse graphs.  The scan goes by chunks of up to 64 members still at degree
-// d: all wavefronts copy the chunk's input rows to LDS (direct-to-LDS loads),
-// wavefront 0 works out which earlier chunk members each one is adjacent to (a
-// 64-bit mask) and the picks (a scalar scan of those masks), and all
-// wavefronts lower the degrees of the picks' neighbours (LDS atomics).  LDS:
-// the remaining degree + 1 of every vertex (0: taken), the round's bucket
-// (16-bit ids, up to kBucketCand), and the chunk's rows (KW x 64 words each,
-// plus one word of padding, so that lane j's row starts in bank j).  order
-// holds the degrees from degree_kernel on entry and the order on exit.
+// d: all wavefronts copy the chunk's input rows to LDS (direct-to-LDS loads)
+// and form, for each member, the mask of earlier chunk members adjacent to it
+// (one ballot a member: lane i tests member i's bit in the member's row);
+// wavefront 0 takes the members with an empty mask at once and decides the
+// others one by one in member order (a pick iff no earlier pick is in its
+// mask); then all wavefronts lower the degrees of the picks' neighbours (LDS
+// atomics on the neighbours still in the graph, found by ANDing each row word
+// with a bitset of the remaining vertices).  LDS: the remaining degree + 1 of
+// every vertex (0: taken), the bitset of remaining vertices, the round's
+// bucket (16-bit ids, up to kBucketCand), and the chunk's rows (KW x 64 words
+// each, plus one word of padding, so that lane j's row starts in bank j).
+// order holds the degrees from degree_kernel on entry and the order on exit.
 constexpr uint32_t kBucketCand = 2048;
+// vertices a thread scans per round: ceil(n / 1024), made odd
+constexpr uint32_t kBucketKpt = ((kMaxN + 1023u) >> 10) | 1u;
 
 struct BucketShared {
+    uint64_t conf[64];  // the chunk: earlier members adjacent to each member
     uint32_t red[16], red2[16];
     uint32_t chk[64];   // the chunk: member ids
     uint32_t cnum, cursor, pos, pad;
@@ -533,6 +540,13 @@ struct BucketShared {
 // LDS the bucket kernels hold besides their dynamic part (BucketShared, rounded up)
 constexpr uint32_t kBucketStaticLds = 1024;
 static_assert(sizeof(BucketShared) <= kBucketStaticLds, "static LDS of the bucket kernels");
+
+// Dynamic LDS words of a bucket kernel for graphs of up to n vertices, before
+// the staged rows: degrees, the bitset of remaining vertices, the bucket.
+__host__ __device__ constexpr uint32_t bucket_fixed_words(uint32_t n)
+{
+    return ((n + 63u) & ~63u) + ((((n + 31u) >> 5) + 63u) & ~63u) + kBucketCand / 2;
+}
 
 template <int KW>
 __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
@@ -543,17 +557,19 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
     const GraphDesc gd = graphs[blockIdx.x];
     const uint32_t n = gd.n;
     if (n == 0) return;
-    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = bcast0(t >> 6);
     constexpr uint32_t NWV = 16;
+    const uint32_t nw = (n + 31u) >> 5;                                      // words that hold vertex bits
     uint32_t* vw = lds;                                                      // n words
-    uint16_t* cand = reinterpret_cast<uint16_t*>(lds + ((n + 63u) & ~63u));  // kBucketCand
-    uint32_t* rowbuf = lds + ((n + 63u) & ~63u) + kBucketCand / 2;
+    uint32_t* alive = lds + ((n + 63u) & ~63u);                              // nw words
+    uint16_t* cand = reinterpret_cast<uint16_t*>(alive + ((nw + 63u) & ~63u)); // kBucketCand
+    uint32_t* rowbuf = lds + bucket_fixed_words(n);
     constexpr uint32_t RS = KW * 64u + 1u; // LDS words between staged rows
     uint32_t* ord = order + gd.ord_off;
     const uint32_t* rw = reinterpret_cast<const uint32_t*>(rows_in + gd.in_off);
     const uint32_t rs32 = 2u * gd.rw64; // 32-bit words of an input row
-    const uint32_t nw = (n + 31u) >> 5; // words that hold vertex bits
     for (uint32_t v = t; v < n; v += 1024) vw[v] = ord[v] + 1u;
+    for (uint32_t w = t; w < nw; w += 1024) alive[w] = (w + 1u < nw || (n & 31u) == 0u) ? ~0u : ((1u << (n & 31u)) - 1u);
     if (t == 0) sh.pos = 0;
     __syncthreads();
     // vertices of this thread for the per-round scans: [v0, v1) (an odd
@@ -562,9 +578,18 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
     const uint32_t kpt = ((n + 1023u) >> 10) | 1u;
     const uint32_t v0 = umin32(t * kpt, n), v1 = umin32(v0 + kpt, n);
     for (;;) {
+        // this thread's remaining degrees + 1, read once a round
+        uint32_t val[kBucketKpt];
+#pragma unroll
+        for (uint32_t k = 0; k < kBucketKpt; k++) {
+            const uint32_t v = v0 + k;
+            const uint32_t x = vw[umin32(v, n - 1u)];
+            val[k] = (k < kpt && v < v1) ? x : 0u;
+        }
         // the largest remaining degree + 1
         uint32_t mx = 0;
-        for (uint32_t v = v0; v < v1; v++) mx = umax32(mx, vw[v]);
+#pragma unroll
+        for (uint32_t k = 0; k < kBucketKpt; k++) mx = umax32(mx, val[k]);
         mx = wave_max(mx);
         if (lane == 0) sh.red[wave] = mx;
         __syncthreads();
@@ -572,23 +597,29 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
         if (mx == 0u) break;
         // its bucket, in increasing id (threads hold consecutive id ranges)
         uint32_t cnt = 0;
-        for (uint32_t v = v0; v < v1; v++) cnt += vw[v] == mx ? 1u : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < kBucketKpt; k++) cnt += val[k] == mx ? 1u : 0u;
         const uint32_t incl = wave_scan_incl(cnt);
         if (lane == 63) sh.red2[wave] = incl;
         __syncthreads();
         const uint32_t wtot = lane < NWV ? sh.red2[lane] : 0u;
         const uint32_t wincl = wave_scan_incl(wtot);
         const uint32_t total = rdlane(wincl, NWV - 1);
-        uint32_t k = rdlane(wincl - wtot, wave) + incl - cnt;
-        for (uint32_t v = v0; v < v1 && k < kBucketCand; v++)
-            if (vw[v] == mx) cand[k++] = (uint16_t)v;
+        uint32_t k0 = rdlane(wincl - wtot, wave) + incl - cnt;
+#pragma unroll
+        for (uint32_t k = 0; k < kBucketKpt; k++) {
+            if (val[k] == mx) {
+                if (k0 < kBucketCand) cand[k0] = (uint16_t)(v0 + k);
+                k0++;
+            }
+        }
         const uint32_t T = umin32(total, kBucketCand);
         if (t == 0) sh.cursor = 0;
         __syncthreads();
         for (;;) {
             // the next chunk: up to 64 members still at the round's degree
             if (wave == 0) {
-                uint32_t i = sh.cursor, cn = 0, mine = 0;
+                uint32_t i = sh.cursor, cn = 0;
                 while (i < T && cn < 64u) {
                     const uint32_t c = i + lane < T ? (uint32_t)cand[i + lane] : 0u;
                     const bool live = i + lane < T && vw[c] == mx;
@@ -610,7 +641,6 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
                         cn = 64u;
                     }
                 }
-                (void)mine;
                 if (lane == 0) {
                     sh.cursor = i;
                     sh.cnum = cn;
@@ -619,6 +649,8 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
             __syncthreads();
             const uint32_t cnum = sh.cnum;
             if (cnum == 0u) break;
+            // member ids, one per lane (lanes past the chunk: member 0)
+            const uint32_t cl = lane < cnum ? sh.chk[lane] : sh.chk[0];
             // rows of the chunk into LDS: row j's words [64 q, 64 q + 64) by
             // one load of a wavefront (words past the row's end read the
             // row's first word and are never looked at); chunks of more than
@@ -637,72 +669,72 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
                 }
                 __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0): this wavefront's rows are in LDS
                 __syncthreads();
+                // member base + j: which earlier members its row holds
+                for (uint32_t j = wave; j < pn; j += NWV) {
+                    const uint32_t w = rowbuf[j * RS + (cl >> 5)];
+                    const uint64_t cj = ballot((((w >> (cl & 31u)) & 1u) != 0u) & (lane < base + j));
+                    if (lane == 0) sh.conf[base + j] = cj;
+                }
+                __syncthreads();
                 if (wave == 0) {
-                    // member j (in this pass): adjacent to which earlier chunk
-                    // members; then the picks, member by member
-                    const uint32_t jl = lane >= base && lane < base + pn ? lane - base : 0u;
-                    const uint32_t* myrow = rowbuf + jl * RS;
-                    const uint32_t cl = lane < cnum ? sh.chk[lane] : 0u;
-                    // eight members a step, their words read before any is
-                    // looked at (the reads overlap instead of waiting in turn)
-                    uint64_t conf = 0;
-                    const uint32_t upto = base + pn;
-                    for (uint32_t i0 = 0; i0 < upto; i0 += 8) {
-                        uint32_t wv[8], ci[8];
-#pragma unroll
-                        for (int k = 0; k < 8; k++) {
-                            const uint32_t i = i0 + (uint32_t)k;
-                            ci[k] = rdlane(cl, i < upto ? i : 0u);
-                            wv[k] = myrow[ci[k] >> 5];
-                        }
-#pragma unroll
-                        for (int k = 0; k < 8; k++) {
-                            const uint32_t i = i0 + (uint32_t)k;
-                            const uint32_t bit = (wv[k] >> (ci[k] & 31u)) & 1u;
-                            conf |= (i < upto && i < lane && lane >= base && lane < upto && bit) ? (1ull << i) : 0ull;
-                        }
-                    }
-                    for (uint32_t j = base; j < base + pn; j++) {
-                        const uint64_t cj = ((uint64_t)rdlane((uint32_t)(conf >> 32), j) << 32) |
-                                            rdlane((uint32_t)conf, j);
+                    // members adjacent to no earlier member are picks; the
+                    // others in member order, against the picks before them
+                    const bool inpass = lane >= base && lane < base + pn;
+                    const uint64_t cme = inpass ? sh.conf[lane] : 0ull;
+                    pick |= ballot(inpass && cme == 0ull);
+                    uint64_t rest = ballot(inpass && cme != 0ull);
+                    while (rest) {
+                        const uint32_t j = (uint32_t)__builtin_ctzll(rest);
+                        rest &= rest - 1ull;
+                        const uint64_t cj = ((uint64_t)rdlane((uint32_t)(cme >> 32), j) << 32) |
+                                            rdlane((uint32_t)cme, j);
                         if ((cj & pick) == 0ull) pick |= 1ull << j;
                     }
                     if (lane == 0) sh.pick = pick;
                 }
                 __syncthreads();
                 pick = sh.pick;
-                // the picks' neighbours lose one degree (picks are pairwise
-                // non-adjacent and no neighbour of an earlier pick, so none
-                // is touched)
+                // the picks' neighbours still in the graph lose one degree
+                // (picks are pairwise non-adjacent and no neighbour of an
+                // earlier pick of the round, so none of them is touched)
                 for (uint32_t j = wave; j < pn; j += NWV) {
                     if (!((pick >> (base + j)) & 1ull)) continue;
                     const uint32_t* r = rowbuf + j * RS;
+                    uint32_t bits[KW];
 #pragma unroll
                     for (int q = 0; q < KW; q++) {
+                        // (every staged word and alive word is read; the
+                        // words past the row's vertex bits are masked)
                         const uint32_t wi = (uint32_t)q * 64u + lane;
-                        uint32_t bits = wi < nw ? r[wi] : 0u;
-                        while (bits) {
-                            const uint32_t u = (wi << 5) | (uint32_t)__builtin_ctz(bits);
-                            bits &= bits - 1u;
-                            if (vw[u] != 0u) atomicSub(&vw[u], 1u);
+                        const uint32_t x = r[wi] & alive[umin32(wi, nw - 1u)];
+                        bits[q] = wi < nw ? x : 0u;
+                    }
+#pragma unroll
+                    for (int q = 0; q < KW; q++) {
+                        const uint32_t wb = ((uint32_t)q * 64u + lane) << 5;
+                        uint32_t b = bits[q];
+                        while (b) {
+                            const uint32_t u = wb | (uint32_t)__builtin_ctz(b);
+                            b &= b - 1u;
+                            atomicSub(&vw[u], 1u);
                         }
                     }
                 }
                 __syncthreads();
             }
-            // the picks, in member order, are the next entries of the order
+            // the picks, in member order, are the next entries of the order;
+            // they leave the graph
             if (wave == 0) {
-                const uint32_t cl = lane < cnum ? sh.chk[lane] : 0u;
-                const bool mine = (pick >> lane) & 1ull;
-                if (mine) {
+                const uint32_t pos = sh.pos;
+                if ((pick >> lane) & 1ull) {
                     const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(pick >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)pick, 0u));
-                    ord[sh.pos + rank] = cl;
+                    ord[pos + rank] = cl;
                     vw[cl] = 0u;
+                    atomicAnd(&alive[cl >> 5], ~(1u << (cl & 31u)));
                 }
+                if (lane == 0) sh.pos = pos + (uint32_t)__builtin_popcountll(pick);
             }
-            __syncthreads();
-            if (t == 0) sh.pos += (uint32_t)__builtin_popcountll(pick);
             __syncthreads();
         }
     }
@@ -2522,7 +2554,7 @@ hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t m
         // wavefront per graph) with as many staged rows per chunk as fit
         const uint32_t kneed = (((max_n + 31u) / 32u) + 63u) / 64u; // words a lane of a row
         const uint32_t kw = kneed <= 4u ? 4u : kneed <= 6u ? 6u : 8u;
-        const uint64_t fixed = 4ull * ((max_n + 63u) & ~63u) + 2ull * kBucketCand;
+        const uint64_t fixed = 4ull * bucket_fixed_words(max_n);
         int dev = 0, lds_max = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
