@@ -741,30 +741,56 @@ __global__ void __launch_bounds__(1024) order_bucket_kernel(const GraphDesc* gra
 }
 
 // Renumbering (Sec. 4.2): row i of the new matrix is row order[i] of the input
-// with column j taken from column order[j].  Block (i, g), one word per thread.
-__global__ void __launch_bounds__(64) relabel_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
-                                                     const uint32_t* order, uint32_t* adj)
+// with column j taken from column order[j].  A workgroup of four wavefronts
+// renumbers kRelabelRows rows of one graph (blockIdx.y): it inverts the order
+// into LDS (pos[order[j]] = j), then each wavefront takes a row at a time,
+// scatters the row's set bits to their positions in an LDS row (one LDS atomic
+// OR a neighbour: work in the row's degree, not in n) and writes the row out.
+// LDS: ceil64(max n) words of pos, then a row of ceil64(max w32) words per
+// wavefront.
+constexpr uint32_t kRelabelRows = 16;
+
+__host__ __device__ constexpr uint32_t relabel_lds_words(uint32_t max_n)
 {
+    return ((max_n + 63u) & ~63u) + 4u * ((((max_n + 31u) >> 5) + 63u) & ~63u);
+}
+
+__global__ void __launch_bounds__(256) relabel_kernel(const GraphDesc* graphs, const uint64_t* rows_in,
+                                                      const uint32_t* order, uint32_t* adj, uint32_t max_n)
+{
+    extern __shared__ uint32_t lds[];
     const GraphDesc gd = graphs[blockIdx.y];
-    const uint32_t i = blockIdx.x;
-    if (i >= gd.n) return;
     const uint32_t n = gd.n;
+    const uint32_t i0 = blockIdx.x * kRelabelRows;
+    if (i0 >= n) return;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = bcast0(t >> 6);
     const uint32_t* ord = order + gd.ord_off;
-    const uint64_t* src = rows_in + gd.in_off + (uint64_t)ord[i] * gd.rw64;
-    uint32_t* dst = adj + gd.adj_off + (uint64_t)i * gd.rstride;
-    for (uint32_t w = threadIdx.x; w < gd.w32; w += blockDim.x) {
-        uint32_t val = 0;
-        for (uint32_t b = 0; b < 32; b++) {
-            const uint32_t j = w * 32u + b;
-            if (j >= n) break;
-            const uint32_t o = ord[j];
-            val |= (uint32_t)((src[o >> 6] >> (o & 63)) & 1ull) << b;
+    uint32_t* pos = lds;
+    for (uint32_t j = t; j < n; j += 256) pos[ord[j]] = j;
+    uint32_t* rowl = lds + ((max_n + 63u) & ~63u) + wave * ((((max_n + 31u) >> 5) + 63u) & ~63u);
+    __syncthreads();
+    const uint32_t W = gd.w32, nw64 = (n + 63u) >> 6;
+    for (uint32_t k = wave; k < kRelabelRows; k += 4) {
+        const uint32_t i = i0 + k;
+        if (i >= n) break;
+        for (uint32_t w = lane; w < W; w += 64) rowl[w] = 0u;
+        // (a wavefront's LDS operations take effect in issue order: the
+        // clearing above precedes every OR below)
+        const uint64_t* src = rows_in + gd.in_off + (uint64_t)ord[i] * gd.rw64;
+        for (uint32_t w = lane; w < nw64; w += 64) {
+            uint64_t x = src[w];
+            while (x) {
+                const uint32_t p = pos[(w << 6) | (uint32_t)__builtin_ctzll(x)];
+                x &= x - 1ull;
+                atomicOr(&rowl[p >> 5], 1u << (p & 31u));
+            }
         }
-        dst[w] = val;
+        uint32_t* dst = adj + gd.adj_off + (uint64_t)i * gd.rstride;
+        for (uint32_t w = lane; w < W; w += 64) dst[w] = rowl[w];
+        // the word after the row holds the vertex's input id, so that the
+        // search gets it with the row
+        if (lane == 0 && gd.rstride > W) dst[W] = ord[i];
     }
-    // the word after the row holds the vertex's input id, so that the search
-    // gets it with the row
-    if (threadIdx.x == 0 && gd.rstride > gd.w32) dst[gd.w32] = ord[i];
 }
 
 // Zero the per-graph results, the histograms, the control block and the
@@ -2612,8 +2638,19 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
 {
     (void)hipGetLastError(); // report only this call's launch errors
     if (max_n == 0) return hipSuccess;
-    hipLaunchKernelGGL(relabel_kernel, dim3(max_n, num_graphs), dim3(64), 0, s, graphs, rows_in,
-                       order, adj);
+    const uint32_t lds = 4u * relabel_lds_words(max_n);
+    if (lds > 65536u) {
+        // more than the default dynamic LDS: allowed once per process
+        static std::once_flag once;
+        static hipError_t err = hipSuccess;
+        std::call_once(once, [] {
+            err = hipFuncSetAttribute((const void*)relabel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(4u * relabel_lds_words(kMaxN)));
+        });
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(relabel_kernel, dim3((max_n + kRelabelRows - 1u) / kRelabelRows, num_graphs), dim3(256), lds,
+                       s, graphs, rows_in, order, adj, max_n);
     return hipGetLastError();
 }
 
