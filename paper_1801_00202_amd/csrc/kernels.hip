@@ -222,6 +222,12 @@ template <int WPL>
 __device__ __forceinline__ void bit_mask(uint32_t v, const uint32_t (&lane_w)[WPL], uint32_t (&m)[WPL])
 {
     const uint32_t wi = v >> 5, b = 1u << (v & 31u);
+    if (WPL == 1) {
+        // one word per lane: the bit written into lane wi of a zero word (v
+        // is wave-uniform, so its lane is a scalar)
+        m[0] = wrlane(0u, b, wi);
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < WPL; c++) m[c] = lane_w[c] == wi ? b : 0u;
 }
