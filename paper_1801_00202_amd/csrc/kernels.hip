@@ -1926,14 +1926,18 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             const uint32_t idv = row_id(crow, v);
             nodes++;
             const uint32_t dp = d;
-            if (d < lds_depth) {
-                uint32_t* f = fl + d * SW;
+            // the parent's sets; an LDS frame is written below in one store,
+            // with the parent's next row (a frame is 16 bytes a lane: one
+            // 128-bit store instead of three 32-bit ones that would meet in
+            // the same LDS banks)
+            uint32_t Pp[WPL], Xp[WPL], Lp[WPL];
 #pragma unroll
-                for (int c = 0; c < WPL; c++) {
-                    f[256 * c] = P[c];
-                    f[256 * c + 1] = X[c];
-                    f[256 * c + 2] = L[c];
-                }
+            for (int c = 0; c < WPL; c++) {
+                Pp[c] = P[c];
+                Xp[c] = X[c];
+                Lp[c] = L[c];
+            }
+            if (d < lds_depth) {
                 idstk = wrlane(idstk, idv, d);
             } else {
                 GU32* fs = spill + ((size_t)chunk * spill_levels + (d - lds_depth)) * SPW;
@@ -2016,14 +2020,15 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
 #pragma unroll
             for (int c = 0; c < WPL; c++) L[c] = P[c] & ~prow[c];
             // the parent's next row, requested before the pivot's, is in:
-            // keep it with the parent frame
-            // (with no next candidate the slot is never read).  A frame in
-            // the spill pool keeps no row: the store then goes to the unused
-            // row slots of the current frame, which only a suspension writes.
+            // the parent's LDS frame is written now, sets and row together
+            // (with no next candidate the row is never read).  A frame in
+            // the spill pool keeps no row: the store then goes to the slot of
+            // the current frame, which only a suspension writes and reads.
             {
                 uint32_t* f = fl + (dp < lds_depth ? dp : lds_depth) * SW;
 #pragma unroll
-                for (int c = 0; c < WPL; c++) f[256 * c + 3] = nrow[c];
+                for (int c = 0; c < WPL; c++)
+                    *reinterpret_cast<uint4*>(f + 256u * c) = make_uint4(Pp[c], Xp[c], Lp[c], nrow[c]);
             }
             cv = first_pos<WPL>(L, lane_lo);
             if (cv == pp) {
