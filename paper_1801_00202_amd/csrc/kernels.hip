@@ -1168,65 +1168,101 @@ __global__ void __launch_bounds__(256) local_build_kernel(const GraphDesc* gpare
 // a child whose P is empty is a leaf, counted here (a maximal clique {l} if
 // X is also empty, else a dead end); any other becomes a node, counted, with
 // its pivot and L = P \ N(p), as a unit of the pool.  The root node counts
-// iff first == 0.  One wavefront per local graph.
+// iff first == 0.  A workgroup of kLocalUnitsWaves wavefronts takes as many
+// consecutive local graphs, one a wavefront; its counts, hash totals and
+// pool slots are gathered in LDS and added to the global counters once (one
+// atomic a counter per workgroup instead of one per child: ten thousand
+// children on the same words would queue at L2).
+constexpr uint32_t kLocalUnitsWaves = 16;
+
 template <int WPL>
-__global__ void __launch_bounds__(64) local_units_kernel(SearchParams sp, const uint32_t* lpx, uint32_t count,
-                                                         uint64_t first, uint64_t last)
+__global__ void __launch_bounds__(64 * kLocalUnitsWaves) local_units_kernel(SearchParams sp, const uint32_t* lpx,
+                                                                           uint32_t count, uint64_t first,
+                                                                           uint64_t last)
 {
-    const uint32_t i = blockIdx.x;
-    const uint32_t lane = lane_id();
+    __shared__ unsigned long long s_hx, s_hs;
+    __shared__ uint32_t s_children, s_nodes, s_count, s_omega, s_units, s_base;
+    const uint32_t lane = lane_id(), wave = bcast0(threadIdx.x >> 6);
+    const uint32_t i = blockIdx.x * kLocalUnitsWaves + wave;
     DevResult* r = sp.results; // every local graph reports to result 0
-    if (i == 0 && first == 0 && last > 0 && lane == 0) atomicAdd(&r->nodes, 1ull);
-    if (i < first || i >= last || i >= count) return;
-    const GraphDesc gd = sp.graphs[i];
-    const uint32_t W = gd.w32, cs = sp.w32cap;
-    const uint32_t* px = lpx + gd.in_off;
+    if (threadIdx.x == 0) {
+        s_hx = s_hs = 0ull;
+        s_children = s_count = s_omega = s_units = 0u;
+        s_nodes = (blockIdx.x == 0 && first == 0 && last > 0) ? 1u : 0u; // the root node
+    }
+    __syncthreads();
+    const bool mine = i >= first && i < last && i < count;
+    GraphDesc gd;
     uint32_t P[WPL], X[WPL], L[WPL];
+    uint32_t rootlid = 0, slot = 0xffffffffu;
+    if (mine) {
+        gd = sp.graphs[i];
+        const uint32_t W = gd.w32;
+        const uint32_t* px = lpx + gd.in_off;
 #pragma unroll
-    for (int c = 0; c < WPL; c++) {
-        const uint32_t w = (uint32_t)c * 64u + lane;
-        P[c] = w < W ? px[w] : 0u;
-        X[c] = w < W ? px[W + w] : 0u;
-    }
-    const uint32_t rootlid = px[2u * W];
-    if (lane == 0) atomicAdd(&r->children, 1ull);
-    if (!any_set<WPL>(P)) {
-        if (!any_set<WPL>(X) && lane == 0) {
-            // the clique {l}
-            const uint32_t id = sp.idmap[gd.idmap_off + rootlid];
-            const uint64_t h = mix64(mix64(1ull) + kGolden + (uint64_t)id);
-            atomicAdd(&r->count, 1ull);
-            atomicXor(&r->hash_xor, (unsigned long long)h);
-            atomicAdd(&r->hash_sum, (unsigned long long)h);
-            atomicMax(&r->omega, 1u);
-            atomicAdd(&sp.hist[gd.hist_off + 1], 1ull);
+        for (int c = 0; c < WPL; c++) {
+            const uint32_t w = (uint32_t)c * 64u + lane;
+            P[c] = w < W ? px[w] : 0u;
+            X[c] = w < W ? px[W + w] : 0u;
         }
-        return;
-    }
-    const int p = node_pivot<WPL>(sp, gd, P, X, lane);
-    const uint32_t* rp = sp.adj + gd.adj_off + (size_t)(uint32_t)p * gd.rstride;
+        rootlid = px[2u * W];
+        if (lane == 0) atomicAdd(&s_children, 1u);
+        if (!any_set<WPL>(P)) {
+            if (!any_set<WPL>(X) && lane == 0) {
+                // the clique {l}
+                const uint32_t id = sp.idmap[gd.idmap_off + rootlid];
+                const uint64_t h = mix64(mix64(1ull) + kGolden + (uint64_t)id);
+                atomicAdd(&s_count, 1u);
+                atomicXor(&s_hx, (unsigned long long)h);
+                atomicAdd(&s_hs, (unsigned long long)h);
+                atomicMax(&s_omega, 1u);
+            }
+        } else {
+            const int p = node_pivot<WPL>(sp, gd, P, X, lane);
+            const uint32_t* rp = sp.adj + gd.adj_off + (size_t)(uint32_t)p * gd.rstride;
 #pragma unroll
-    for (int c = 0; c < WPL; c++) {
-        const uint32_t w = (uint32_t)c * 64u + lane;
-        L[c] = (w < W) ? (P[c] & ~rp[w]) : 0u;
+            for (int c = 0; c < WPL; c++) {
+                const uint32_t w = (uint32_t)c * 64u + lane;
+                L[c] = (w < W) ? (P[c] & ~rp[w]) : 0u;
+            }
+            uint32_t sl = 0;
+            if (lane == 0) {
+                atomicAdd(&s_nodes, 1u);
+                sl = atomicAdd(&s_units, 1u);
+            }
+            slot = bcast0(sl);
+        }
     }
-    uint32_t pos = 0;
-    if (lane == 0) {
-        atomicAdd(&r->nodes, 1ull);
-        pos = atomicAdd(&sp.ctl->pool_size, 1u);
-        atomicAdd(&sp.ctl->work, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_units) {
+            s_base = atomicAdd(&sp.ctl->pool_size, s_units);
+            atomicAdd(&sp.ctl->work, s_units);
+        }
+        if (s_children) atomicAdd(&r->children, (unsigned long long)s_children);
+        if (s_nodes) atomicAdd(&r->nodes, (unsigned long long)s_nodes);
+        if (s_count) {
+            atomicAdd(&r->count, (unsigned long long)s_count);
+            atomicXor(&r->hash_xor, s_hx);
+            atomicAdd(&r->hash_sum, s_hs);
+            atomicMax(&r->omega, s_omega);
+            atomicAdd(&sp.hist[sp.graphs[0].hist_off + 1], (unsigned long long)s_count);
+        }
     }
-    pos = bcast0(pos);
-    uint32_t* rec = sp.rec + (size_t)pos * sp.rec_words;
-    if (lane == 0) rec[0] = i;
+    __syncthreads();
+    if (slot != 0xffffffffu) {
+        const uint32_t W = gd.w32, cs = sp.w32cap;
+        uint32_t* rec = sp.rec + (size_t)(s_base + slot) * sp.rec_words;
+        if (lane == 0) rec[0] = i;
 #pragma unroll
-    for (int c = 0; c < WPL; c++) {
-        const uint32_t w = (uint32_t)c * 64u + lane;
-        if (w < W) {
-            rec[kRecHeader + w] = (w == (rootlid >> 5)) ? (1u << (rootlid & 31u)) : 0u; // R = {l}
-            rec[kRecHeader + cs + w] = P[c];
-            rec[kRecHeader + 2 * cs + w] = X[c];
-            rec[kRecHeader + 3 * cs + w] = L[c];
+        for (int c = 0; c < WPL; c++) {
+            const uint32_t w = (uint32_t)c * 64u + lane;
+            if (w < W) {
+                rec[kRecHeader + w] = (w == (rootlid >> 5)) ? (1u << (rootlid & 31u)) : 0u; // R = {l}
+                rec[kRecHeader + cs + w] = P[c];
+                rec[kRecHeader + 2 * cs + w] = X[c];
+                rec[kRecHeader + 3 * cs + w] = L[c];
+            }
         }
     }
 }
@@ -2744,7 +2780,8 @@ hipError_t launch_local_units(const SearchParams& sp, const uint32_t* lpx, uint3
     (void)hipGetLastError(); // report only this call's launch errors
     if (count == 0) return hipSuccess;
     if (search_chunks(max_w32) != 1) return hipErrorInvalidValue; // local graphs have one-chunk layouts
-    hipLaunchKernelGGL(local_units_kernel<1>, dim3(count), dim3(64), 0, s, sp, lpx, count, first, last);
+    hipLaunchKernelGGL(local_units_kernel<1>, dim3((count + kLocalUnitsWaves - 1u) / kLocalUnitsWaves),
+                       dim3(64 * kLocalUnitsWaves), 0, s, sp, lpx, count, first, last);
     return hipGetLastError();
 }
 

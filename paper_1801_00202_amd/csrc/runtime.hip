@@ -410,6 +410,8 @@ struct mce_graph_s {
     int local_state = 0;
     uint32_t lcount = 0, lmax_w32 = 0, lmax_n = 0;
     DevBuf d_ldesc, d_ladj, d_lord, d_lidmap, d_lpx;
+    std::vector<GraphDesc> ldesc_host; // the source of d_ldesc's copy, kept while it may be in flight
+    hipEvent_t ev_local = nullptr;     // recorded after the local graphs' build
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float prepare_ms = 0.f;
     bool prepared_timed = false;
@@ -422,6 +424,7 @@ struct mce_graph_s {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (ev_local) (void)hipEventDestroy(ev_local);
     }
 };
 
@@ -696,10 +699,11 @@ int ensure_events(mce_graph_s* h)
 }
 
 // The local graphs of a single graph of more than 4096 vertices, built once
-// (on stream s, which is then waited for): the degrees and root-child flags
-// of its positions come to the host, which lays the local graphs out (each
-// root child l: |N(l)| + 1 vertices) and gives up if one would be wider than
-// the one-chunk layout; the device then builds them.
+// on stream s: the degrees and root-child flags of its positions come to the
+// host (a wait), which lays the local graphs out (each root child l:
+// |N(l)| + 1 vertices) and gives up if one would be wider than the one-chunk
+// layout; the device then builds them, and ev_local marks the end of the
+// build (solves on other streams wait for it).
 int ensure_local(mce_graph_s* h, hipStream_t s)
 {
     if (h->local_state != 0) return MCE_OK;
@@ -750,8 +754,12 @@ int ensure_local(mce_graph_s* h, hipStream_t s)
     HIP_TRY(launch_local_build(h->d_desc.as<GraphDesc>(), h->d_adj.as<uint32_t>(), h->d_order.as<uint32_t>(), n,
                                h->d_ldesc.as<GraphDesc>(), (uint32_t)ld.size(), h->d_ladj.as<uint32_t>(),
                                h->d_lord.as<uint32_t>(), h->d_lidmap.as<uint32_t>(), h->d_lpx.as<uint32_t>(), s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // no wait here: the build's end is an event that solves wait for (on
+    // this stream, a no-op), and the host layout stays with the handle
+    if (!h->ev_local) HIP_TRY(hipEventCreateWithFlags(&h->ev_local, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(h->ev_local, s));
     h->lcount = (uint32_t)ld.size();
+    h->ldesc_host = std::move(ld);
     h->lmax_w32 = mw;
     h->lmax_n = mn;
     h->local_state = 1;
@@ -806,6 +814,7 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
     // local graphs of its root children
     if (!sub_bits && (rc = ensure_local(g, s)) != MCE_OK) return rc;
     const bool local = !sub_bits && g->local_state == 1;
+    if (local) HIP_TRY(hipStreamWaitEvent(s, g->ev_local, 0));
     if (local) use_graph = false;
     uint32_t floor = g->spill_floor;
     bool full_depth = g->spill_full_depth;
@@ -1512,8 +1521,11 @@ int mce_release(mce_graph_t g)
         std::lock_guard<std::mutex> lk(g->mu);
         if (g->jobs_in_flight.load() != 0) return MCE_E_BUSY;
         // every solve waits for its own stream before it returns; only the
-        // prepare work (ordering, renumbering) may still be in flight
+        // prepare work (ordering, renumbering) and, after a solve that failed
+        // before its launch, the build of the local graphs may still be in
+        // flight
         if (g->ev[1] && !g->prepared_timed) (void)hipEventSynchronize(g->ev[1]);
+        if (g->ev_local) (void)hipEventSynchronize(g->ev_local);
     }
     delete g;
     return MCE_OK;
