@@ -1345,8 +1345,10 @@ __device__ __forceinline__ void wg_unlock(WgHdr* h, uint32_t lane)
 
 // Per-wavefront LDS layout (32-bit words):
 //   [kOffHist, +128)   histogram of clique sizes < kHistLds (u64)
-//   [kOffBuf, +kCliqueSlots)  clique buffer (16-bit halves of input-id bitsets)
-//   [kOffTrash, +64)   one word per lane for stores that must go nowhere
+//   [kOffBuf, +kCliqueSlots)  clique buffer (path-id lists or 16-bit halves
+//                      of input-id bitsets)
+//   [kOffTrash, +64)   one word per lane for stores that must go nowhere (and
+//                      the unit's R as ids while the buffer is emptied)
 //   [kOffCtx, +32)     WaveCtx: totals and bookkeeping used off the hot path
 //   [kOffSave, +128)   the search loop's lane registers while it is suspended:
 //                      idstk (64 words), then cent (64 words)
@@ -1357,6 +1359,16 @@ __device__ __forceinline__ void wg_unlock(WgHdr* h, uint32_t lane)
 constexpr uint32_t kOffHist = 0, kOffBuf = kHistLds * 2, kOffTrash = kOffBuf + kCliqueSlots,
                    kOffCtx = kOffTrash + 64, kOffSave = kOffCtx + 32;
 static_assert(kOffSave + 128 == kWaveFixedWords, "layout");
+
+// Clique buffer entries: cent (one word a clique) = start << 16 | flags and
+// length.  A list entry (one word a lane layouts, a clique of at most
+// kCliqueListMax vertices whose path is in the LDS window) holds the input ids
+// pushed on the way down from the unit's node and the last vertex's, one a
+// word, in path order; the unit's own R is the fourth word of the current
+// frame slot.  Any other entry holds the non-empty 16-bit halves of the
+// clique's input-id bitset, in lane order.
+constexpr uint32_t kEntryList = 0x8000u, kEntryLen = 0x7fffu;
+constexpr uint32_t kCliqueListMax = 16;
 
 struct WaveCtx {
     unsigned long long count, nodes, children; // totals of graph g not yet folded into HBM
@@ -1405,21 +1417,79 @@ __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restr
     WaveCtx* ctx = wave_ctx(wl);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     const bool mine = lane < nent;
-    const uint32_t st = mine ? (cent >> 16) : 0u, cnt = mine ? (cent & 0xffffu) : 0u;
+    const bool lst = mine && (cent & kEntryList) != 0u;
+    const uint32_t st = mine ? (cent >> 16) : 0u, cnt = mine ? (cent & kEntryLen) : 0u;
+    // List entries: the unit's R (the fourth word of the current frame slot,
+    // one word a lane, written when the search loop returned) in increasing
+    // order into the sink words; then each list lane sorts its path's ids
+    // with those (at most kCliqueListMax in all) by a bitonic network.
+    uint32_t r = 0;
+    uint32_t* sink = wl + kOffTrash;
+    if (ballot(lst) != 0ull) {
+        const uint32_t* cur = wl + kWaveFixedWords + (size_t)sp.lds_depth * sp.slot_words;
+        const uint32_t bw = lane < gd.w32 ? cur[4u * lane + 3u] : 0u;
+        uint64_t nz = ballot(bw != 0u);
+        uint32_t bl = 0;
+        while (nz) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(nz);
+            nz &= nz - 1ull;
+            uint32_t word = rdlane(bw, l);
+            while (word) {
+                bl = wrlane(bl, (l << 5) | (uint32_t)__builtin_ctz(word), r);
+                word &= word - 1u;
+                r++;
+            }
+        }
+        sink[lane] = bl;
+    }
+    uint32_t srt[kCliqueListMax];
+    if (lst) {
+#pragma unroll
+        for (uint32_t j = 0; j < kCliqueListMax; j++) {
+            const uint32_t x = j < cnt ? buf[st + j] : sink[umin32(j - cnt, 63u)];
+            srt[j] = j < cnt + r ? x : 0xffffffffu;
+        }
+#pragma unroll
+        for (uint32_t kk = 2; kk <= kCliqueListMax; kk <<= 1) {
+#pragma unroll
+            for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+                for (uint32_t i = 0; i < kCliqueListMax; i++) {
+                    const uint32_t l = i ^ jj;
+                    if (l > i) {
+                        const uint32_t x = srt[i], y = srt[l];
+                        const bool up = (i & kk) == 0u;
+                        srt[i] = up ? umin32(x, y) : umax32(x, y);
+                        srt[l] = up ? umax32(x, y) : umin32(x, y);
+                    }
+                }
+            }
+        }
+    }
     // clique size, then the hash chain over the ids in increasing order
     uint32_t k = 0;
-    for (uint32_t i = 0; i < cnt; i++) k += (uint32_t)__builtin_popcount(buf[st + i] & 0xffffu);
+    if (lst) {
+        k = cnt + r;
+    } else {
+        for (uint32_t i = 0; i < cnt; i++) k += (uint32_t)__builtin_popcount(buf[st + i] & 0xffffu);
+    }
     uint64_t h = 0;
     if (mine) {
         h = mix64((uint64_t)k);
-        for (uint32_t i = 0; i < cnt; i++) {
-            const uint32_t e = buf[st + i];
-            const uint32_t base = (e >> 16) << 4;
-            uint32_t bits = e & 0xffffu;
-            while (bits) {
-                const uint32_t id = base + (uint32_t)__builtin_ctz(bits);
-                h = mix64(h + kGolden + (uint64_t)(idm ? idm[id] : id));
-                bits &= bits - 1u;
+        if (lst) {
+#pragma unroll
+            for (uint32_t j = 0; j < kCliqueListMax; j++)
+                if (j < k) h = mix64(h + kGolden + (uint64_t)(idm ? idm[srt[j]] : srt[j]));
+        } else {
+            for (uint32_t i = 0; i < cnt; i++) {
+                const uint32_t e = buf[st + i];
+                const uint32_t base = (e >> 16) << 4;
+                uint32_t bits = e & 0xffffu;
+                while (bits) {
+                    const uint32_t id = base + (uint32_t)__builtin_ctz(bits);
+                    h = mix64(h + kGolden + (uint64_t)(idm ? idm[id] : id));
+                    bits &= bits - 1u;
+                }
             }
         }
     }
@@ -1469,14 +1539,20 @@ __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restr
             unsigned long long q = vb + kincl - k;
             sp.offs[ob + 2ull * lane] = q;
             sp.offs[ob + 2ull * lane + 1ull] = q + k;
-            for (uint32_t i = 0; i < cnt; i++) {
-                const uint32_t e = buf[st + i];
-                const uint32_t base = (e >> 16) << 4;
-                uint32_t bits = e & 0xffffu;
-                while (bits) {
-                    const uint32_t id = base + (uint32_t)__builtin_ctz(bits);
-                    sp.verts[q++] = idm ? idm[id] : id;
-                    bits &= bits - 1u;
+            if (lst) {
+#pragma unroll
+                for (uint32_t j = 0; j < kCliqueListMax; j++)
+                    if (j < k) sp.verts[q + j] = idm ? idm[srt[j]] : srt[j];
+            } else {
+                for (uint32_t i = 0; i < cnt; i++) {
+                    const uint32_t e = buf[st + i];
+                    const uint32_t base = (e >> 16) << 4;
+                    uint32_t bits = e & 0xffffu;
+                    while (bits) {
+                        const uint32_t id = base + (uint32_t)__builtin_ctz(bits);
+                        sp.verts[q++] = idm ? idm[id] : id;
+                        bits &= bits - 1u;
+                    }
                 }
             }
         }
@@ -1623,8 +1699,14 @@ __device__ __attribute__((noinline)) uint32_t cold_check(const SearchParams* __r
                 Xd[c] = Xs[c] | L1[c];
                 Rs[c] = Rb[c];
             }
-            // R of frame s: drop the children pushed from frames s..d-1
-            for (uint32_t j = s; j < d; j++) clear_bit<WPL>(Rs, child_id(j), lane);
+            // R of frame s: one word a lane, the unit's R with the children
+            // pushed from frames 0..s-1; else the current R without the
+            // children pushed from frames s..d-1
+            if (WPL == 1) {
+                for (uint32_t j = 0; j < s; j++) set_bit<WPL>(Rs, child_id(j), lane);
+            } else {
+                for (uint32_t j = s; j < d; j++) clear_bit<WPL>(Rs, child_id(j), lane);
+            }
             bool ok;
             if (asker != 0u && !gave) {
                 // the unit is in transit until the asker takes it: count it
@@ -1862,6 +1944,10 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
         cent = save[64 + lane];
     }
     uint32_t chunk = bcast0(ctx->spill_chunk);
+    // one word a lane: Rb is the unit's own R throughout (a clique's path
+    // ids go to its buffer entry; donations add a frame's path ids), and rsz
+    // its size.  Wider layouts keep Rb = the current node's R.
+    const uint32_t rsz = WPL == 1 ? wave_sum((uint32_t)__builtin_popcount(Rb[0])) : 0u;
     uint32_t kids = 0;   // children examined since the last return
     uint32_t nodes = 0;  // nodes created since then
     uint32_t spills = 0; // frames written to the spill pool since then
@@ -1913,10 +1999,13 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
                 cv = first_pos<WPL>(L, lane_lo);
                 load_row(cv >= 0 ? (uint32_t)cv : 0u, crow);
             }
-            uint32_t m[WPL];
-            bit_mask<WPL>(idp, lane_w, m);
+            if (WPL > 1) {
+                uint32_t m[WPL];
+                bit_mask<WPL>(idp, lane_w, m);
 #pragma unroll
-            for (int c = 0; c < WPL; c++) Rb[c] &= ~m[c];
+                for (int c = 0; c < WPL; c++) Rb[c] &= ~m[c];
+            }
+            (void)idp;
             continue;
         }
         // v is in L, L is a subset of P, and X is disjoint from P: taking v
@@ -1988,11 +2077,14 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
                 spills++;
             }
             d++;
-            uint32_t mi[WPL];
-            bit_mask<WPL>(idv, lane_w, mi);
+            if (WPL > 1) {
+                uint32_t mi[WPL];
+                bit_mask<WPL>(idv, lane_w, mi);
+#pragma unroll
+                for (int c = 0; c < WPL; c++) Rb[c] |= mi[c];
+            }
 #pragma unroll
             for (int c = 0; c < WPL; c++) {
-                Rb[c] |= mi[c];
                 P[c] = P2[c];
                 X[c] = X2[c];
             }
@@ -2075,58 +2167,85 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             }
         } else {
             if (!any_set<WPL>(X2)) {
-                // P' and X' empty: R u {v} is maximal.  R is the bitset Rb over
-                // input ids; its non-empty 16-bit halves, in lane order, are the
-                // clique's sorted ids.  A clique has at most 2 W of them: up to
-                // four chunks the buffer is emptied whenever fewer than 2 W
-                // slots are left; wider graphs count the clique's halves first
-                // and, when they do not fit, put the child back and empty the
-                // buffer (a clique larger than the whole buffer is an error).
+                // P' and X' empty: R u {v} is maximal.  One word a lane: a
+                // clique of at most kCliqueListMax vertices whose path is in
+                // the LDS window is written as a list entry (the path's ids,
+                // lanes 0..d-1 of the id stack, then v's; lane j writes word
+                // j).  Otherwise the entry holds the non-empty 16-bit halves
+                // of the clique's bitset over input ids, in lane order (the
+                // clique's sorted ids); one word a lane rebuilds R first from
+                // the unit's R and the path.  A clique has at most 2 W halves:
+                // up to four chunks the buffer is emptied whenever fewer than
+                // the longest entry's slots are left; wider graphs count the
+                // clique's halves first and, when they do not fit, put the
+                // child back and empty the buffer (a clique larger than the
+                // whole buffer is an error).
                 const uint32_t idv = row_id(crow, v);
-                uint32_t mi[WPL], cwd[WPL];
-                uint64_t blo[WPL], bhi[WPL];
-                uint32_t halves = 0;
-                bit_mask<WPL>(idv, lane_w, mi);
-#pragma unroll
-                for (int c = 0; c < WPL; c++) {
-                    cwd[c] = Rb[c] | mi[c];
-                    blo[c] = ballot((cwd[c] & 0xffffu) != 0u);
-                    bhi[c] = ballot((cwd[c] >> 16) != 0u);
-                    halves += (uint32_t)__builtin_popcountll(blo[c]) + (uint32_t)__builtin_popcountll(bhi[c]);
+                bool listed = false;
+                if (WPL == 1 && d < lds_depth && rsz + d + 1u <= kCliqueListMax) {
+                    *(lane <= d ? buf + used + lane : trash + lane) = lane < d ? idstk : idv;
+                    cent = wrlane(cent, (used << 16) | kEntryList | (d + 1u), nent);
+                    used += d + 1u;
+                    listed = true;
                 }
-                if (WPL >= 4 && used + halves > kCliqueSlots) {
+                if (!listed) {
+                    uint32_t mi[WPL], cwd[WPL];
+                    uint64_t blo[WPL], bhi[WPL];
+                    uint32_t halves = 0;
+                    bit_mask<WPL>(idv, lane_w, mi);
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) cwd[c] = Rb[c] | mi[c];
+                    if (WPL == 1) {
+                        for (uint32_t j = 0; j < d; j++) {
+                            const uint32_t id = j < lds_depth
+                                                    ? rdlane(idstk, j)
+                                                    : bcast0(spill[((size_t)chunk * spill_levels + (j - lds_depth)) * SPW + 3u]);
+                            uint32_t mj[WPL];
+                            bit_mask<WPL>(id, lane_w, mj);
+                            cwd[0] |= mj[0];
+                        }
+                    }
 #pragma unroll
                     for (int c = 0; c < WPL; c++) {
-                        L[c] ^= m[c];
-                        P[c] ^= m[c];
-                        X[c] ^= m[c];
+                        blo[c] = ballot((cwd[c] & 0xffffu) != 0u);
+                        bhi[c] = ballot((cwd[c] >> 16) != 0u);
+                        halves += (uint32_t)__builtin_popcountll(blo[c]) + (uint32_t)__builtin_popcountll(bhi[c]);
                     }
-                    kids--;
-                    why = used == 0u ? kUnitBig : kUnitFlush;
-                    break;
-                }
-                const uint32_t start = used;
+                    if (WPL >= 4 && used + halves > kCliqueSlots) {
 #pragma unroll
-                for (int c = 0; c < WPL; c++) {
-                    const uint32_t lo = cwd[c] & 0xffffu, hi = cwd[c] >> 16;
-                    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                                               (uint32_t)(blo[c] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)blo[c], 0u)) +
-                                           __builtin_amdgcn_mbcnt_hi(
-                                               (uint32_t)(bhi[c] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bhi[c], 0u));
-                    const uint32_t plo = used + below;
-                    const uint32_t phi = plo + (lo != 0u ? 1u : 0u);
-                    const uint32_t hw = (((uint32_t)c * 64u + lane) << 1);
-                    *(lo != 0u ? buf + plo : trash + lane) = (hw << 16) | lo;
-                    *(hi != 0u ? buf + phi : trash + lane) = ((hw + 1u) << 16) | hi;
-                    used += (uint32_t)__builtin_popcountll(blo[c]) + (uint32_t)__builtin_popcountll(bhi[c]);
+                        for (int c = 0; c < WPL; c++) {
+                            L[c] ^= m[c];
+                            P[c] ^= m[c];
+                            X[c] ^= m[c];
+                        }
+                        kids--;
+                        why = used == 0u ? kUnitBig : kUnitFlush;
+                        break;
+                    }
+                    const uint32_t start = used;
+#pragma unroll
+                    for (int c = 0; c < WPL; c++) {
+                        const uint32_t lo = cwd[c] & 0xffffu, hi = cwd[c] >> 16;
+                        const uint32_t below =
+                            __builtin_amdgcn_mbcnt_hi((uint32_t)(blo[c] >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)blo[c], 0u)) +
+                            __builtin_amdgcn_mbcnt_hi((uint32_t)(bhi[c] >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bhi[c], 0u));
+                        const uint32_t plo = used + below;
+                        const uint32_t phi = plo + (lo != 0u ? 1u : 0u);
+                        const uint32_t hw = (((uint32_t)c * 64u + lane) << 1);
+                        *(lo != 0u ? buf + plo : trash + lane) = (hw << 16) | lo;
+                        *(hi != 0u ? buf + phi : trash + lane) = ((hw + 1u) << 16) | hi;
+                        used += (uint32_t)__builtin_popcountll(blo[c]) + (uint32_t)__builtin_popcountll(bhi[c]);
+                    }
+                    cent = wrlane(cent, (start << 16) | (used - start), nent);
                 }
-                cent = wrlane(cent, (start << 16) | (used - start), nent);
                 nent++;
                 cv = nv;
 #pragma unroll
                 for (int c = 0; c < WPL; c++) crow[c] = nrow[c];
                 // a full clique buffer is emptied at once
-                if (nent == 64u || (WPL < 4 && used + 2u * W > kCliqueSlots)) {
+                if (nent == 64u || (WPL < 4 && used + umax32(2u * W, WPL == 1 ? kCliqueListMax : 0u) > kCliqueSlots)) {
                     why = kUnitFlush;
                     break;
                 }
@@ -2171,6 +2290,9 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
         ctx->d = d;
         ctx->budget = budget;
         ctx->rcount = rcount;
+    } else if (WPL == 1) {
+        // the unit's R, for the flush of the clique buffer that follows
+        cur[4u * lane + 3u] = Rb[0];
     }
     save[64 + lane] = cent;
     ctx->nent = nent;
