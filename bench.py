@@ -51,14 +51,20 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "search_kernel_gnp1000_traffic.
 
 
 def kernel_source_hash() -> str:
-    """sha256 (16 hex digits) of the search kernel's source: the part of
-    kernels.hip from the search section to the launchers (the other kernels
-    do not change what the search kernel's counters read)."""
-    with open(KERNEL_SRC, "rb") as f:
-        src = f.read()
-    a = src.index(b"// ------------------------------------------------------ the search -------")
-    b = src.index(b"// ---------------------------------------------------------- launchers ----")
-    return hashlib.sha256(src[a:b]).hexdigest()[:16]
+    """sha256 (16 hex digits) of the device code the search kernel is built
+    from: kernels.hip up to its launchers, and mce_internal.h, with comments
+    and blank space taken out (so that a comment does not count as a change,
+    and any change to the device code does, helpers included)."""
+    parts = []
+    for path, cut in ((KERNEL_SRC, True), (os.path.join(os.path.dirname(KERNEL_SRC), "mce_internal.h"), False)):
+        with open(path) as f:
+            src = f.read()
+        if cut:
+            src = src[:src.index("// ---------------------------------------------------------- launchers ----")]
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        parts.append(" ".join(src.split()))
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
 def algorithmic_word_ops(res: dict, n: int) -> int:

@@ -2151,7 +2151,8 @@ __device__ __attribute__((noinline)) uint32_t search_unit(const SearchParams* __
             // the parent's LDS frame is written now, sets and row together
             // (with no next candidate the row is never read).  A frame in
             // the spill pool keeps no row: the store then goes to the slot of
-            // the current frame, which only a suspension writes and reads.
+            // the current frame, which the loop writes whenever it returns,
+            // before anything reads it.
             {
                 uint32_t* f = fl + (dp < lds_depth ? dp : lds_depth) * SW;
 #pragma unroll
