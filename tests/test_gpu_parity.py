@@ -70,6 +70,52 @@ def test_moon_moser_small(mce, orc):
         g.release()
 
 
+@pytest.mark.parametrize("depth", [0, 3, 17])
+def test_clique_entry_boundaries(mce, orc, depth):
+    """One word a lane: a clique of at most 16 vertices whose path is in the
+    LDS window is reported as the list of its path's ids (sorted with the
+    unit's R when the buffer is emptied); a larger or deeper one rebuilds R
+    from the path, spilled levels included.  Cliques of 15, 16 and 17
+    vertices and deep random ones, with a window of 3 frames (most cliques
+    deeper), the automatic one and 17 (every path of K_17 in LDS), against the
+    oracle; the enumerated lists too."""
+    if depth:
+        mce.set_option("lds_depth", depth)
+    cases = [synth.complete(15), synth.complete(16), synth.complete(17), synth.moon_moser(5),
+             synth.disjoint_union(synth.complete(16), synth.complete(17), synth.moon_moser(3)),
+             synth.gnp(100, 0.8, 3), synth.gnp(200, 0.6, 4)]
+    for rows in cases:
+        res, g = solve(mce, rows)
+        try:
+            same(res, orc.greedy(rows))
+        finally:
+            g.release()
+    rows = synth.disjoint_union(synth.complete(16), synth.complete(17), synth.gnp(60, 0.6, 7))
+    g = mce.Graph(rows)
+    try:
+        res, verts, offs = g.enumerate()
+        assert not res["truncated"]
+        ref, ref_list = orc.greedy_list(rows)
+        same(res, ref)
+        assert sorted(mce.cliques_from_output(verts, offs, res["count"])) == sorted(ref_list)
+    finally:
+        g.release()
+
+
+def test_moon_moser_16_list_entries(mce, orc):
+    """3^16 cliques of exactly 16 vertices, each a list entry of the largest
+    size (window of 17 frames), against the closed forms and the oracle."""
+    mce.set_option("lds_depth", 17)
+    rows = synth.moon_moser(16)
+    res, g = solve(mce, rows)
+    try:
+        assert res["count"] == 3 ** 16 and res["nodes"] == (3 ** 16 - 1) // 2 and res["omega"] == 16
+        assert res["hist"][16] == 3 ** 16 and sum(res["hist"]) == 3 ** 16
+        same(res, orc.greedy(rows, threads=8))
+    finally:
+        g.release()
+
+
 def test_large_n_two_words_per_lane(mce, orc):
     # n > 2048 takes the two-words-per-lane path
     for n, p, seed in [(2049, 0.01, 1), (3000, 0.005, 2), (4096, 0.004, 3)]:
