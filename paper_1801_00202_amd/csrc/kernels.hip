@@ -413,7 +413,22 @@ __global__ void __launch_bounds__(64) order_lds_kernel(const GraphDesc* graphs, 
     if (n == 0) return;
     const uint64_t* in = rows_in + gd.in_off;
     const uint64_t words = (uint64_t)n * gd.rw64;
-    for (uint64_t i = lane_id(); i < words; i += 64) rows_l[i] = in[i];
+    // sixteen loads in flight a lane before their stores (one at a time, the
+    // copy of a 1000-vertex graph's rows took longer than its rounds)
+    constexpr uint32_t kStageBatch = 16;
+    for (uint64_t i0 = lane_id(); i0 < words; i0 += 64u * kStageBatch) {
+        uint64_t w[kStageBatch];
+#pragma unroll
+        for (uint32_t k = 0; k < kStageBatch; k++) {
+            const uint64_t i = i0 + 64u * k;
+            w[k] = i < words ? in[i] : 0ull;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kStageBatch; k++) {
+            const uint64_t i = i0 + 64u * k;
+            if (i < words) rows_l[i] = w[k];
+        }
+    }
     __syncthreads();
     order_rounds<KPL>(gd, rows_l, order + gd.ord_off);
 }
@@ -772,7 +787,20 @@ __global__ void __launch_bounds__(256) relabel_kernel(const GraphDesc* graphs, c
     const uint32_t t = threadIdx.x, lane = lane_id(), wave = bcast0(t >> 6);
     const uint32_t* ord = order + gd.ord_off;
     uint32_t* pos = lds;
-    for (uint32_t j = t; j < n; j += 256) pos[ord[j]] = j;
+    // eight loads in flight a thread before their stores
+    for (uint32_t j0 = t; j0 < n; j0 += 256u * 8u) {
+        uint32_t o[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t j = j0 + 256u * k;
+            o[k] = j < n ? ord[j] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t j = j0 + 256u * k;
+            if (j < n) pos[o[k]] = j;
+        }
+    }
     uint32_t* rowl = lds + ((max_n + 63u) & ~63u) + wave * ((((max_n + 31u) >> 5) + 63u) & ~63u);
     __syncthreads();
     const uint32_t W = gd.w32, nw64 = (n + 63u) >> 6;
