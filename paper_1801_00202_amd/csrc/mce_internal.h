@@ -182,9 +182,15 @@ inline uint32_t search_lds_bytes(uint32_t wave_lds_words, uint32_t rec_words, ui
 // Host-side launchers (kernels.hip).
 hipError_t launch_validate(const uint64_t* rows, uint32_t n, uint32_t rw, unsigned int* flag,
                            hipStream_t s);
-// max_words: the largest n * rw64 of the graphs (their input rows' words)
+// max_words: the largest n * rw64 of the graphs (their input rows' words).
+// nbr: for graphs of more than 4096 vertices, room for cap 16-bit entries
+// a vertex (indexed like order), cap = order_list_cap(max_n), used for
+// neighbour lists during the ordering, and done: a word a graph; nullptr
+// (or cap 0): none.
+uint32_t order_list_cap(uint32_t max_n);
 hipError_t launch_order(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n, uint64_t max_words,
-                        const uint64_t* rows_in, uint32_t* order, hipStream_t s);
+                        const uint64_t* rows_in, uint32_t* order, uint16_t* nbr, uint32_t cap, uint32_t* done,
+                        hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t value, hipStream_t s);
 hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
                           const uint64_t* rows_in, const uint32_t* order, uint32_t* adj,

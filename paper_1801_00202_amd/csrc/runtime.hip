@@ -374,7 +374,7 @@ struct mce_graph_s {
     std::vector<GraphDesc> desc;
     uint32_t max_n = 0, max_w32 = 0;
     uint64_t in_words = 0, adj_words = 0, ord_words = 0, hist_total = 0;
-    DevBuf d_desc, d_in, d_adj, d_order;
+    DevBuf d_desc, d_in, d_adj, d_order, d_nbr;
     // workspace of the solve
     DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params, d_sub;
     HostPinned h_params; // staging of the search parameters of direct (not replayed) solves
@@ -1148,8 +1148,15 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
     }
     uint64_t max_words = 0;
     for (const GraphDesc& gd : desc) max_words = std::max<uint64_t>(max_words, (uint64_t)gd.n * gd.rw64);
+    // neighbour lists for the degree-bucket ordering of graphs of more than
+    // 4096 vertices and a word a graph after them (kept with the handle: the
+    // ordering runs asynchronously)
+    const uint32_t cap = order_list_cap(h->max_n);
+    const uint64_t lbytes = (2ull * cap * ord + 3u) & ~3ull;
+    if (cap != 0u && (rc = h->d_nbr.ensure(lbytes + 4ull * h->num_graphs)) != MCE_OK) return rc;
     HIP_TRY(launch_order(h->d_desc.as<GraphDesc>(), h->num_graphs, h->max_n, max_words, h->d_in.as<uint64_t>(),
-                         h->d_order.as<uint32_t>(), s));
+                         h->d_order.as<uint32_t>(), cap != 0u ? h->d_nbr.as<uint16_t>() : nullptr, cap,
+                         cap != 0u ? reinterpret_cast<uint32_t*>(h->d_nbr.as<char>() + lbytes) : nullptr, s));
     HIP_TRY(launch_relabel(h->d_desc.as<GraphDesc>(), h->num_graphs, h->max_n, h->d_in.as<uint64_t>(),
                            h->d_order.as<uint32_t>(), h->d_adj.as<uint32_t>(), s));
     HIP_TRY(hipEventRecord(h->ev[1], s));
@@ -1664,7 +1671,8 @@ extern "C" int mce_count_noalloc(uint32_t n, const uint64_t* rows, uint32_t row_
     HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (bad) return MCE_E_INVAL;
-    HIP_TRY(launch_order(h->d_desc.as<GraphDesc>(), 1, n, (uint64_t)n * row_words, rows, h->d_order.as<uint32_t>(), s));
+    HIP_TRY(launch_order(h->d_desc.as<GraphDesc>(), 1, n, (uint64_t)n * row_words, rows, h->d_order.as<uint32_t>(),
+                         nullptr, 0, nullptr, s));
     HIP_TRY(launch_relabel(h->d_desc.as<GraphDesc>(), 1, n, rows, h->d_order.as<uint32_t>(), h->d_adj.as<uint32_t>(), s));
     HIP_TRY(hipEventRecord(h->ev[1], s));
     if ((rc = finish_prepare_timing_locked(h)) != MCE_OK) return rc;

@@ -170,6 +170,19 @@ def test_wide_rows(mce, orc, n, p, seed):
     g.release()
 
 
+@pytest.mark.parametrize("deg", (127, 128, 129))
+def test_bucket_list_boundary(mce, orc, deg):
+    # n > 4096: the degree-bucket ordering stages neighbour lists of 128
+    # slots when the largest degree is at most 128, else rows
+    rows = _hub(10000, 0.001, 61, 4321, deg)
+    res, g = solve(mce, rows)
+    try:
+        assert list(g.order()) == list(orc.order(rows))
+        same(res, orc.greedy(rows, threads=8))
+    finally:
+        g.release()
+
+
 def _hub(n, p, seed, hub, deg):
     """G(n, p) with vertex `hub` joined to exactly `deg` vertices (a seeded
     choice): the largest degree, so the hub is position 0 of the ordering and
