@@ -400,6 +400,27 @@ def test_schedule_stress(mce, orc, opts):
         g.release()
 
 
+@pytest.mark.parametrize("opts", [{"lds_depth": 0}, {"lds_depth": 1}, {"lds_depth": 0, "waves_per_block": 4}])
+def test_spill_pool_rerun(mce, orc, opts):
+    """With no LDS window (or one frame) every busy wavefront needs a spill
+    chunk: the first launch's pool (64 chunks) runs out, the search stops
+    with the spill error and is run again with a chunk for every wavefront
+    (two launches, the oracle's result); the handle keeps that pool, so its
+    next solve takes one launch."""
+    for k, v in opts.items():
+        mce.set_option(k, v)
+    rows = synth.gnp(200, 0.5, 3)
+    ref = orc.greedy(rows)
+    g = mce.Graph(rows)
+    try:
+        for attempts in (2, 1):
+            same(g.count(), ref)
+            st = mce.last_stats()
+            assert st["attempts"] == attempts and st["spills"] > 0
+    finally:
+        g.release()
+
+
 def test_graph_replay_after_other_solves(mce, orc):
     """With the solve captured as a hipGraph for every count (graph = 2), a
     count, an enumeration and a count on one handle: both counts equal the
