@@ -3017,9 +3017,10 @@ hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max
                        uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s)
 {
     (void)hipGetLastError(); // report only this call's launch errors
-    // writers per graph: enough to fill the queue quickly, few per graph in a batch
+    // writers per graph: about a unit each for a single graph (a writer
+    // takes a few microseconds a unit), few per graph in a batch
     uint32_t k = 1;
-    while (k < 64 && k < max_units && (uint64_t)num_graphs * k < 4096) k <<= 1;
+    while (k < 1024 && k < max_units && (uint64_t)num_graphs * k < 4096) k <<= 1;
     switch (search_chunks(max_w32)) {
     case 1:
         hipLaunchKernelGGL(root_plan_kernel<1>, dim3(num_graphs), dim3(64), 0, s, sp, first, last, max_units);
