@@ -13,6 +13,11 @@ generator.
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build runs on
 one GPU.
 
+``--g300-full K/N`` runs part K of N of the whole G(300, 0.8) graph (about
+10^12 maximal cliques, some 1000 s of search: too long for one call, and for
+the oracle) as subproblems, and ``--g300-combine`` adds the parts up; see
+``split_pieces``.
+
 ``--copy-probe`` instead times a plain device-to-device copy of known size;
 run under ``rocprofv3 --pmc FETCH_SIZE`` (then ``WRITE_SIZE``) it calibrates the
 HBM byte counters that the ``traffic`` figure of the search kernel uses.
@@ -375,6 +380,110 @@ def config_legs(mce, synth, np, oracle_mod) -> dict:
     return out
 
 
+def split_pieces(adj, limit: int):
+    """Cut the GreedyBB search tree of a graph into subproblems: the top of
+    the tree is expanded here in the library's own order (Alg. 4 with the
+    GreedyBB pivot of Sec. 4.3: the first vertex of X, else of P, in
+    position order; branch set L = P minus N(pivot), in increasing
+    position; P and X updated after each child, steps 12-13) until every
+    node left has at most `limit` candidates; those nodes are the pieces.
+    adj: boolean adjacency over positions of the ordering.  Returns the
+    pieces as (R, P, X) position lists and the expanded part's counters
+    (nodes including the root, children, dead ends); a maximal clique at
+    the expanded levels is an error (none occurs where the pieces are
+    large).  Every clique is then found by the GPU below some piece, and
+    the counters of the pieces plus the expanded part's are those of the
+    whole search."""
+    import numpy as np
+    n = adj.shape[0]
+    pieces, nodes, children, dead = [], 0, 0, 0
+    stack = [([], np.ones(n, dtype=bool), np.zeros(n, dtype=bool))]
+    while stack:
+        R, P, X = stack.pop()
+        if R and int(P.sum()) <= limit:
+            pieces.append((R, [int(v) for v in np.flatnonzero(P)], [int(v) for v in np.flatnonzero(X)]))
+            continue
+        nodes += 1
+        xs, ps = np.flatnonzero(X), np.flatnonzero(P)
+        piv = xs[0] if xs.size else ps[0]
+        P, X = P.copy(), X.copy()
+        for v in np.flatnonzero(P & ~adj[piv]):
+            children += 1
+            P2, X2 = P & adj[v], X & adj[v]
+            if not P2.any():
+                if not X2.any():
+                    raise RuntimeError("a maximal clique above the pieces: lower the limit")
+                dead += 1
+            else:
+                stack.append((R + [int(v)], P2, X2))
+            P[v] = False
+            X[v] = True
+    return pieces, {"nodes": nodes, "children": children, "dead_ends": dead}
+
+
+def g300_full(mce, synth, np, part: int, parts: int, limit: int = 200) -> dict:
+    """Part `part` of `parts` of the whole G(300, 0.8) graph, seed 0: the
+    pieces of split_pieces (sorted by size, dealt out in turn) counted with
+    mce_count_subproblem, their results added (hash_xor by XOR, hash_sum
+    mod 2^64).  Part 0 also carries the expanded levels' counters."""
+    rows = synth.gnp(300, 0.8, 0)
+    g = mce.Graph(rows)
+    order = g.order().astype(np.int64)
+    adj = synth.unpack_rows(rows)[np.ix_(order, order)]
+    pieces, top = split_pieces(adj, limit)
+    pieces.sort(key=lambda q: (len(q[1]), q[0]))
+    mine = pieces[part::parts]
+    tot = {"count": 0, "nodes": 0, "children": 0, "dead_ends": 0, "hash_xor": 0, "hash_sum": 0, "omega": 0,
+           "hist": [0] * 301}
+    secs = 0.0
+    for i, (R, P, X) in enumerate(mine):
+        t0 = time.perf_counter()
+        r = g.count_subproblem(R, P, X)
+        secs += time.perf_counter() - t0
+        for k in ("count", "nodes", "children", "dead_ends"):
+            tot[k] += r[k]
+        tot["hash_xor"] ^= r["hash_xor"]
+        tot["hash_sum"] = (tot["hash_sum"] + r["hash_sum"]) % (1 << 64)
+        tot["omega"] = max(tot["omega"], r["omega"])
+        for j, c in enumerate(r["hist"]):
+            tot["hist"][j] += c
+        if (i + 1) % 100 == 0 or i + 1 == len(mine):
+            print("g300 part %d/%d: %d of %d pieces, %.1f s of search, %.4g cliques" % (
+                part, parts, i + 1, len(mine), secs, tot["count"]), file=sys.stderr, flush=True)
+    g.release()
+    if part == 0:
+        for k in ("nodes", "children", "dead_ends"):
+            tot[k] += top[k]
+    return {"g300_part": part, "parts": parts, "limit": limit, "pieces": len(mine), "pieces_total": len(pieces),
+            "expanded": top, "seconds": secs, **tot}
+
+
+def g300_combine(paths) -> dict:
+    """The parts' results added up into the whole graph's."""
+    parts = []
+    for path in paths:
+        with open(path) as f:
+            parts.append(json.loads([line for line in f if line.startswith("{")][-1]))
+    n = parts[0]["parts"]
+    assert sorted(p["g300_part"] for p in parts) == list(range(n)), "every part once"
+    out = {"workload": "G(n=300, p=0.8) seed 0, whole graph", "parts": n, "limit": parts[0]["limit"],
+           "pieces": sum(p["pieces"] for p in parts), "expanded": parts[0]["expanded"]}
+    for k in ("count", "nodes", "children", "dead_ends", "seconds"):
+        out[k] = sum(p[k] for p in parts)
+    out["hash_xor"] = 0
+    for p in parts:
+        out["hash_xor"] ^= p["hash_xor"]
+    out["hash_sum"] = sum(p["hash_sum"] for p in parts) % (1 << 64)
+    out["omega"] = max(p["omega"] for p in parts)
+    hist = [sum(p["hist"][j] for p in parts) for j in range(len(parts[0]["hist"]))]
+    while hist and hist[-1] == 0:
+        hist.pop()
+    out["hist"] = hist
+    out["cliques_per_s"] = out["count"] / out["seconds"]
+    out["nodes_per_s"] = out["nodes"] / out["seconds"]
+    return out
+
+
 def pivot_rules(mce, d_rows, reps: int) -> dict:
     """The workload graph under each pivot rule of Sec. 4.3 (automatic
     schedule): the same cliques, different trees; solve time of one handle."""
@@ -437,7 +546,15 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="automatic schedule instead of mce_autotune's")
     ap.add_argument("--opts", default="", metavar="K=V,...",
                     help="fixed schedule (library options such as waves_per_block=8,blocks=512); no tuning")
+    ap.add_argument("--g300-full", default="", metavar="K/N",
+                    help="part K of N of the whole G(300, 0.8) graph as subproblems (one JSON line)")
+    ap.add_argument("--g300-combine", nargs="+", default=None, metavar="FILE",
+                    help="add up the JSON lines of the --g300-full parts")
     args = ap.parse_args()
+
+    if args.g300_combine:
+        print(json.dumps(g300_combine(args.g300_combine)))
+        return
 
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported" % args.gpus,
@@ -457,6 +574,10 @@ def main():
     mce.reset_options(watchdog_ms=120000)
     if args.only_serving:
         print(json.dumps({"serving": serving(mce, synth, np, args.serving_requests, warm=100)}))
+        return
+    if args.g300_full:
+        k, n = (int(x) for x in args.g300_full.split("/"))
+        print(json.dumps(g300_full(mce, synth, np, k, n)))
         return
     peaks = None if args.no_peaks else measured_peaks()
     wl = WORKLOADS[args.workload]

@@ -191,3 +191,34 @@ def test_python_edge_list_helper():
     assert adj.sum() == 4 and adj[0, 1] and adj[3, 2]
     with pytest.raises(ValueError):
         synth.edge_list_to_rows(3, [(1, 1)])
+
+
+@pytest.mark.parametrize("n,p,seed,limit", [(60, 0.7, 3, 30), (90, 0.5, 4, 40)])
+def test_split_pieces_cover_the_search(orc, n, p, seed, limit):
+    """The cut of the search tree used by the whole-G(300, 0.8) measurement
+    (bench.split_pieces), checked on the CPU with the oracle: the pieces'
+    subproblems plus the expanded levels' counters give the whole search's
+    count, nodes, children, dead ends, hashes and histogram."""
+    import bench
+    rows = synth.gnp(n, p, seed)
+    order = np.asarray(orc.order(rows), dtype=np.int64)
+    adj = synth.unpack_rows(rows)[np.ix_(order, order)]
+    pieces, top = bench.split_pieces(adj, limit)
+    assert len(pieces) > 5 and top["nodes"] > 1
+    pos_rows = synth.pack_rows(adj)
+    tot = dict(top, count=0, hash_xor=0, hash_sum=0, omega=0)
+    hist = [0] * (n + 1)
+    for R, P, X in pieces:
+        r = orc.subproblem(pos_rows, R, P, X, ids=order)
+        for k in ("count", "nodes", "children", "dead_ends"):
+            tot[k] += r[k]
+        tot["hash_xor"] ^= r["hash_xor"]
+        tot["hash_sum"] = (tot["hash_sum"] + r["hash_sum"]) % (1 << 64)
+        tot["omega"] = max(tot["omega"], r["omega"])
+        for j, c in enumerate(r["hist"]):
+            hist[j] += c
+    ref = orc.greedy(rows)
+    for k in ("count", "nodes", "children", "dead_ends", "hash_xor", "hash_sum", "omega"):
+        assert tot[k] == ref[k], k
+    rh = list(ref["hist"])
+    assert hist[:len(rh)] == rh and not any(hist[len(rh):])

@@ -166,6 +166,41 @@ def test_gnp300_p08_node_golden(mce):
         g.release()
 
 
+@pytest.mark.parametrize("n,p,seed,limit", [(120, 0.8, 5, 80), (200, 0.6, 6, 120)])
+def test_split_pieces_add_up_to_whole_search(mce, orc, n, p, seed, limit):
+    """The cut of the search tree that the whole-G(300, 0.8) measurement
+    uses (bench.split_pieces: the top levels expanded in the library's
+    order, the nodes left counted with mce_count_subproblem) adds up to the
+    whole graph's count, counters, hashes and histogram, and to the oracle."""
+    import bench
+    rows = synth.gnp(n, p, seed)
+    g = mce.Graph(rows)
+    try:
+        order = g.order().astype(np.int64)
+        assert list(order) == list(orc.order(rows))
+        adj = synth.unpack_rows(rows)[np.ix_(order, order)]
+        pieces, top = bench.split_pieces(adj, limit)
+        assert len(pieces) > 10 and top["nodes"] > 1
+        tot = dict(top, count=0, hash_xor=0, hash_sum=0, omega=0, hist=[0] * (n + 1))
+        for R, P, X in pieces:
+            r = g.count_subproblem(R, P, X)
+            for k in ("count", "nodes", "children", "dead_ends"):
+                tot[k] += r[k]
+            tot["hash_xor"] ^= r["hash_xor"]
+            tot["hash_sum"] = (tot["hash_sum"] + r["hash_sum"]) % (1 << 64)
+            tot["omega"] = max(tot["omega"], r["omega"])
+            for j, c in enumerate(r["hist"]):
+                tot["hist"][j] += c
+        full = g.count()
+        ref = orc.greedy(rows, threads=8)
+        for k in ("count", "nodes", "children", "dead_ends", "hash_xor", "hash_sum", "omega"):
+            assert tot[k] == full[k] == ref[k], k
+        hist = list(full["hist"])
+        assert tot["hist"][:len(hist)] == hist and not any(tot["hist"][len(hist):])
+    finally:
+        g.release()
+
+
 def test_subproblem_at_root_is_whole_search(mce, orc):
     rows = synth.gnp(150, 0.5, 2)
     order = orc.order(rows)
