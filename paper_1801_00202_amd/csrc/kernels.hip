@@ -1272,9 +1272,27 @@ __global__ void __launch_bounds__(256) local_build_kernel(const GraphDesc* gpare
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the lane's words of the row (at most 512 words, eight a lane) are
+        // requested together (words past the row's end read its first word
+        // and are dropped), then their bits ranked.  (Requesting the next
+        // member's words before ranking these gained nothing more.)
+        static_assert(kMaxN / 32u <= 8u * 64u, "a whole-graph row in eight words a lane");
         const uint32_t* rq = grow + (size_t)q * G.rstride;
-        for (uint32_t w = lane; w < W; w += 64) {
-            uint32_t x = rq[w] & Sw[w];
+        uint32_t xs[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t w = lane + 64u * k, wc = w < W ? w : 0u;
+            xs[k] = rq[wc];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t w = lane + 64u * k;
+            xs[k] = w < W ? xs[k] & Sw[w] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t w = lane + 64u * k;
+            uint32_t x = xs[k];
             while (x) {
                 const uint32_t b = (uint32_t)__builtin_ctz(x);
                 x &= x - 1u;
