@@ -65,8 +65,10 @@ extern "C" {
 
 /* Tuning options (mce_set_option / mce_get_option).  Values apply to calls
  * made after the change; 0 restores the automatic choice where noted. */
-#define MCE_OPT_WAVES_PER_BLOCK 1  /* search wavefronts per workgroup, 1..16 (0 = auto) */
-#define MCE_OPT_BLOCKS 2           /* persistent search workgroups (0 = fill the device) */
+#define MCE_OPT_WAVES_PER_BLOCK 1  /* search wavefronts per workgroup, 1..16 (0 = auto: 8, or 2 for
+                                      searches on local graphs) */
+#define MCE_OPT_BLOCKS 2           /* persistent search workgroups (0 = fill the device; searches
+                                      on local graphs: four workgroups a CU) */
 #define MCE_OPT_LDS_DEPTH 3        /* stack levels kept in LDS per wavefront, 0..64 (rest spill to HBM);
                                       with 16 wavefronts a workgroup a window of 2 levels or less
                                       is refused (the solve returns MCE_E_INVAL) */
