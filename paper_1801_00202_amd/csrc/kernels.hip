@@ -2749,8 +2749,12 @@ __global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(Search
                 if (lane == 0) lds_st(&hdr->out, 0u);
             }
         }
-        if (g != bcast0(ctx->g)) {
-            cold_fold(spp, wl);
+        const uint32_t gprev = bcast0(ctx->g);
+        if (g != gprev) {
+            // the totals are folded into HBM only when the result slot
+            // changes: the local graphs of a graph all report into its slot,
+            // and a fold a unit would queue their atomics on the same words
+            if (gprev != 0xffffffffu && sp.graphs[g].res != sp.graphs[gprev].res) cold_fold(spp, wl);
             if (lane == 0) ctx->g = g;
         }
         if (lane == 0) ctx->units += 1;
