@@ -183,6 +183,23 @@ def test_bucket_list_boundary(mce, orc, deg):
         g.release()
 
 
+def test_bucket_lists_and_rows_in_one_batch(mce, orc):
+    # a batch of graphs of more than 4096 vertices where some are ordered on
+    # neighbour lists (largest degree at most 128) and others on rows: the
+    # list kernel flags the graphs it ordered and the row kernel takes the
+    # others, graph by graph
+    graphs = [synth.gnp(6000, 0.001, 71), _hub(5000, 0.001, 72, 99, 300), synth.gnp(4500, 0.002, 73),
+              _hub(7000, 0.0005, 74, 7, 129)]
+    b = mce.Graph(batch=graphs)
+    try:
+        out = b.count()
+        for i, rows in enumerate(graphs):
+            assert list(b.order(i)) == list(orc.order(rows))
+            same(out[i], orc.greedy(rows, threads=8))
+    finally:
+        b.release()
+
+
 def _hub(n, p, seed, hub, deg):
     """G(n, p) with vertex `hub` joined to exactly `deg` vertices (a seeded
     choice): the largest degree, so the hub is position 0 of the ordering and
