@@ -314,7 +314,7 @@ int mce_clear_tuning(mce_graph_t g);
  * graph), MCE_E_NOMEM, MCE_E_DEVICE.
  */
 #define MCE_NOALLOC_MAX_N 2048u
-#define MCE_NOALLOC_SCRATCH_BYTES 33554432u /* 32 MiB */
+#define MCE_NOALLOC_SCRATCH_BYTES 50331648u /* 48 MiB */
 int mce_count_noalloc(uint32_t n, const uint64_t *rows, uint32_t row_words, mce_result_t *res,
                       void *hip_stream);
 

@@ -1710,35 +1710,77 @@ __device__ __attribute__((noinline)) void cold_flush(const SearchParams* __restr
 }
 
 // Fold the wavefront's totals of graph ctx->g (counts, hash totals, omega,
-// histogram) into HBM and clear them.
+// histogram) into HBM and clear them.  Every value is read before the first
+// atomic is issued, so that the atomics leave back to back and the wavefront
+// waits for them once: a read issued after an atomic would wait for it, and
+// when a search ends every wavefront folds into the same result slot at once,
+// where each such wait is a pass through the queue on that slot's cache line.
 __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restrict__ spp, uint32_t* wl)
 {
+    static_assert(kHistLds == 64, "one histogram entry per lane");
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
     WaveCtx* ctx = wave_ctx(wl);
     const uint32_t g = bcast0(ctx->g);
     if (g == 0xffffffffu) return;
     unsigned long long* hist_l = reinterpret_cast<unsigned long long*>(wl + kOffHist);
-    const uint64_t x = ctx->hx, s = ctx->hs;
-    const uint64_t hoff = sp.graphs[g].hist_off;
+    const unsigned long long hv = hist_l[lane];
+    const unsigned long long count = ctx->count, nodes = ctx->nodes, children = ctx->children;
+    const unsigned long long x = ctx->hx, s = ctx->hs;
+    const uint32_t omega = ctx->omega;
+    unsigned long long* hp = sp.hist + sp.graphs[g].hist_off + lane;
+    DevResult* r = sp.results + sp.graphs[g].res;
+    asm volatile("" : : "v"(hp), "v"(r)); // both addresses are formed before the first atomic
     if (lane == 0) {
-        DevResult* r = sp.results + sp.graphs[g].res;
-        if (ctx->count) atomicAdd(&r->count, ctx->count);
-        if (ctx->nodes) atomicAdd(&r->nodes, ctx->nodes);
-        if (ctx->children) atomicAdd(&r->children, ctx->children);
-        if (x) atomicXor(&r->hash_xor, (unsigned long long)x);
-        if (s) atomicAdd(&r->hash_sum, (unsigned long long)s);
-        if (ctx->omega) atomicMax(&r->omega, ctx->omega);
+        if (count) atomicAdd(&r->count, count);
+        if (nodes) atomicAdd(&r->nodes, nodes);
+        if (children) atomicAdd(&r->children, children);
+        if (x) atomicXor(&r->hash_xor, x);
+        if (s) atomicAdd(&r->hash_sum, s);
+        if (omega) atomicMax(&r->omega, omega);
+    }
+    if (hv) atomicAdd(hp, hv);
+    if (lane == 0) {
         ctx->count = ctx->nodes = ctx->children = 0;
         ctx->hx = ctx->hs = 0;
         ctx->omega = 0;
     }
-    for (uint32_t i = lane; i < kHistLds; i += 64) {
-        const unsigned long long hv = hist_l[i];
-        if (hv) {
-            atomicAdd(&sp.hist[hoff + i], hv);
-            hist_l[i] = 0ull;
-        }
+    hist_l[lane] = 0ull;
+}
+
+// The wavefront's exit record (WaveExit): its unfolded totals of graph ctx->g
+// and its counters, written with plain stores; exit_fold_kernel adds the
+// records up after the launch.  `first` and `last` are lane 0's wall-clock
+// ticks of its first unit start and last unit end (0: no unit).
+__device__ __attribute__((noinline)) void cold_exit(const SearchParams* __restrict__ spp, uint32_t* wl,
+                                                    uint32_t gwave, uint64_t t_start, uint64_t first, uint64_t last)
+{
+    const SearchParams& sp = *spp;
+    const uint32_t lane = lane_id();
+    const WaveCtx* ctx = wave_ctx(wl);
+    WaveExit* e = sp.exits + gwave;
+    const uint32_t g = bcast0(ctx->g);
+    e->hist[lane] = reinterpret_cast<const unsigned long long*>(wl + kOffHist)[lane];
+    if (lane == 0) {
+        const bool none = g == 0xffffffffu;
+        e->res = none ? kNoSlot : sp.graphs[g].res;
+        e->omega = ctx->omega;
+        e->hist_off = none ? 0ull : sp.graphs[g].hist_off;
+        e->count = ctx->count;
+        e->nodes = ctx->nodes;
+        e->children = ctx->children;
+        e->hash_xor = ctx->hx;
+        e->hash_sum = ctx->hs;
+        e->units = ctx->units;
+        e->donations = ctx->donations;
+        e->spills = ctx->spills;
+        e->checks = ctx->checks;
+        e->flushes = ctx->flushes;
+        e->busy = ctx->busy;
+        const uint64_t t_exit = wall_clock64();
+        e->run = t_exit - t_start;
+        e->ramp = (first ? first : t_exit) - t_start;
+        e->tail = first ? t_exit - last : 0ull;
     }
 }
 
@@ -2809,19 +2851,160 @@ __global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(Search
         wg_unlock(hdr, lane);
         if (abort) break;
     }
-    cold_fold(spp, wl);
+    cold_exit(spp, wl, gwave, t_start, times.first, times.last);
     set_state(kWaveExited);
-    if (lane == 0) {
-        if (ctx->units) atomicAdd(&sp.ctl->units, ctx->units);
-        if (ctx->donations) atomicAdd(&sp.ctl->donations, ctx->donations);
-        if (ctx->spills) atomicAdd(&sp.ctl->spill_levels_written, ctx->spills);
-        if (ctx->checks) atomicAdd(&sp.ctl->checks, (unsigned long long)ctx->checks);
-        if (ctx->flushes) atomicAdd(&sp.ctl->flushes, (unsigned long long)ctx->flushes);
-        const uint64_t t_exit = wall_clock64();
-        atomicAdd(&sp.ctl->busy_ticks, ctx->busy);
-        atomicAdd(&sp.ctl->run_ticks, (unsigned long long)(t_exit - t_start));
-        atomicAdd(&sp.ctl->ramp_ticks, (unsigned long long)((times.first ? times.first : t_exit) - t_start));
-        atomicAdd(&sp.ctl->tail_ticks, (unsigned long long)(times.first ? t_exit - times.last : 0));
+}
+
+// One thread per exit record, 256 a workgroup.  The counters are summed over
+// the workgroup and added to the control block once; when all records of the
+// workgroup that hold totals report to the same result slot and histogram
+// (one graph, as in every search of local graphs), so are the totals, else each
+// record adds its own.
+constexpr uint32_t kFoldThreads = 256;
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_xor64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v ^= __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = umax32(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+__global__ void __launch_bounds__(kFoldThreads) exit_fold_kernel(SearchParams sp, uint32_t waves)
+{
+    constexpr uint32_t NW = kFoldThreads / 64;
+    constexpr uint32_t kSums = 14; // 10 counters, then count, nodes, children, hash_sum
+    __shared__ unsigned long long part[NW][kSums + 2];
+    __shared__ unsigned long long hpart[NW][kHistLds];
+    __shared__ unsigned long long hoff_min, hoff_max;
+    __shared__ uint32_t res_min, res_max;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    const uint32_t base = blockIdx.x * kFoldThreads;
+    const uint32_t r = base + t;
+    const bool have = r < waves;
+    const WaveExit* e = sp.exits + (have ? r : 0u);
+    if (t == 0) {
+        res_min = kNoSlot;
+        res_max = 0u;
+        hoff_min = ~0ull;
+        hoff_max = 0ull;
+    }
+    __syncthreads();
+    const uint32_t res = have ? e->res : kNoSlot;
+    const bool holds = res != kNoSlot;
+    const unsigned long long hoff = holds ? e->hist_off : 0ull;
+    if (holds) {
+        atomicMin(&res_min, res);
+        atomicMax(&res_max, res);
+        atomicMin(&hoff_min, hoff);
+        atomicMax(&hoff_max, hoff);
+    }
+    unsigned long long v[kSums];
+    v[0] = have ? e->units : 0ull;
+    v[1] = have ? e->donations : 0ull;
+    v[2] = have ? e->spills : 0ull;
+    v[3] = have ? e->checks : 0ull;
+    v[4] = have ? e->flushes : 0ull;
+    v[5] = have ? e->busy : 0ull;
+    v[6] = have ? e->run : 0ull;
+    v[7] = have ? e->ramp : 0ull;
+    v[8] = have ? e->tail : 0ull;
+    v[9] = 0ull;
+    v[10] = holds ? e->count : 0ull;
+    v[11] = holds ? e->nodes : 0ull;
+    v[12] = holds ? e->children : 0ull;
+    v[13] = holds ? e->hash_sum : 0ull;
+    const unsigned long long hx = holds ? e->hash_xor : 0ull;
+    const uint32_t om = holds ? e->omega : 0u;
+    __syncthreads();
+    const bool one_slot = res_min != kNoSlot && res_min == res_max && hoff_min == hoff_max;
+    const uint32_t nsum = one_slot ? kSums : 10u;
+#pragma unroll
+    for (uint32_t k = 0; k < kSums; k++)
+        if (k < nsum) {
+            const unsigned long long w = wave_sum64(v[k]);
+            if (lane == 0) part[wv][k] = w;
+        }
+    if (one_slot) {
+        const unsigned long long wx = wave_xor64(hx);
+        const uint32_t wm = wave_max32(om);
+        if (lane == 0) {
+            part[wv][kSums] = wx;
+            part[wv][kSums + 1] = wm;
+        }
+        // histogram: lane i adds entry i of the wavefront's 64 records (the
+        // index is clamped instead of branched on, so that the loads are
+        // independent and leave back to back)
+        unsigned long long h = 0ull;
+        const uint32_t r0 = base + wv * 64u;
+#pragma unroll 16
+        for (uint32_t k = 0; k < 64u; k++) {
+            const uint32_t rr = r0 + k;
+            const unsigned long long x = sp.exits[rr < waves ? rr : waves - 1u].hist[lane];
+            h += rr < waves ? x : 0ull;
+        }
+        hpart[wv][lane] = h;
+    } else if (holds) {
+        DevResult* d = sp.results + res;
+        if (v[10]) atomicAdd(&d->count, v[10]);
+        if (v[11]) atomicAdd(&d->nodes, v[11]);
+        if (v[12]) atomicAdd(&d->children, v[12]);
+        if (v[13]) atomicAdd(&d->hash_sum, v[13]);
+        if (hx) atomicXor(&d->hash_xor, hx);
+        if (om) atomicMax(&d->omega, om);
+        for (uint32_t i = 0; i < kHistLds; i++) {
+            const unsigned long long hv = e->hist[i];
+            if (hv) atomicAdd(&sp.hist[hoff + i], hv);
+        }
+    }
+    __syncthreads();
+    if (t < kSums + 2u) {
+        unsigned long long w = 0ull;
+        if (t < nsum || (one_slot && t < kSums + 2u)) {
+#pragma unroll
+            for (uint32_t q = 0; q < NW; q++) {
+                const unsigned long long pq = part[q][t];
+                w = t == kSums ? (w ^ pq) : t == kSums + 1u ? (pq > w ? pq : w) : w + pq;
+            }
+        }
+        if (w != 0ull) {
+            QueueCtl* c = sp.ctl;
+            DevResult* d = sp.results + (one_slot ? res_min : 0u);
+            switch (t) {
+            case 0: atomicAdd(&c->units, w); break;
+            case 1: atomicAdd(&c->donations, w); break;
+            case 2: atomicAdd(&c->spill_levels_written, w); break;
+            case 3: atomicAdd(&c->checks, w); break;
+            case 4: atomicAdd(&c->flushes, w); break;
+            case 5: atomicAdd(&c->busy_ticks, w); break;
+            case 6: atomicAdd(&c->run_ticks, w); break;
+            case 7: atomicAdd(&c->ramp_ticks, w); break;
+            case 8: atomicAdd(&c->tail_ticks, w); break;
+            case 10: atomicAdd(&d->count, w); break;
+            case 11: atomicAdd(&d->nodes, w); break;
+            case 12: atomicAdd(&d->children, w); break;
+            case 13: atomicAdd(&d->hash_sum, w); break;
+            case kSums: atomicXor(&d->hash_xor, w); break;
+            case kSums + 1: atomicMax(&d->omega, (uint32_t)w); break;
+            default: break;
+            }
+        }
+    }
+    if (one_slot && wv == 0) {
+        unsigned long long h = 0ull;
+#pragma unroll
+        for (uint32_t q = 0; q < NW; q++) h += hpart[q][lane];
+        if (h) atomicAdd(&sp.hist[hoff_min + lane], h);
     }
 }
 
@@ -3157,6 +3340,15 @@ hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint3
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(search_fn(max_w32, sp.pivot_rule), dim3(blocks), dim3(64 * waves_per_block), lds, s, sp,
                        d_sp);
+    return hipGetLastError();
+}
+
+hipError_t launch_exit_fold(const SearchParams& sp, uint32_t waves, hipStream_t s)
+{
+    (void)hipGetLastError(); // report only this call's launch errors
+    if (waves == 0) return hipSuccess;
+    hipLaunchKernelGGL(exit_fold_kernel, dim3((waves + kFoldThreads - 1u) / kFoldThreads), dim3(kFoldThreads), 0, s,
+                       sp, waves);
     return hipGetLastError();
 }
 

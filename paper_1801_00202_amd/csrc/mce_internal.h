@@ -122,6 +122,22 @@ struct Mailbox {
 };
 constexpr unsigned int kMailNone = 0u, kMailUnit = 1u, kMailRefused = 2u;
 
+// Exit record of one search wavefront: its totals of the graph it worked on
+// last (not yet added to that graph's result slot) and its counters.  The
+// exit-fold kernel that runs after the search adds the records up, so that the
+// wavefronts, which leave within microseconds of each other, issue no atomics
+// on the same few words at once.
+constexpr unsigned int kNoSlot = 0xffffffffu;
+struct WaveExit {
+    unsigned int res, omega; // result slot (kNoSlot: the wavefront held no graph), largest clique
+    unsigned long long hist_off; // where hist adds into SearchParams.hist
+    unsigned long long count, nodes, children, hash_xor, hash_sum;
+    unsigned long long units, donations, spills, checks, flushes; // QueueCtl counters
+    unsigned long long busy, run, ramp, tail;                     // wall-clock ticks (QueueCtl *_ticks)
+    unsigned long long hist[kHistLds];
+};
+static_assert(sizeof(WaveExit) == 8 * (16 + kHistLds), "WaveExit layout");
+
 // QueueCtl.error bits
 constexpr unsigned int kErrSpill = 1u; // spill pool exhausted: rerun with a larger pool
 constexpr unsigned int kErrDepth = 2u; // stack deeper than a spill chunk: rerun with chunks of full depth
@@ -160,6 +176,7 @@ struct SearchParams {
     uint32_t refresh_children; // children a workgroup processes between two looks at its mailbox
     uint32_t poll_iters;       // idle iterations between two looks at the end-of-search counter
     uint32_t* wave_state;     // per wavefront: kWave* phase (for deadline reports), or null
+    WaveExit* exits;          // per wavefront (blockIdx.x * waves per workgroup + wavefront)
     uint32_t pivot_rule;      // kPivot*
     uint32_t pad0;
     // host-written word in coherent pinned host memory, or null: non-zero asks
@@ -213,6 +230,9 @@ hipError_t launch_local_units(const SearchParams& sp, const uint32_t* lpx, uint3
                               uint64_t first, uint64_t last, hipStream_t s);
 hipError_t launch_search(const SearchParams& sp, const SearchParams* d_sp, uint32_t max_w32, uint32_t blocks,
                          uint32_t waves_per_block, hipStream_t s);
+// Adds the exit records of the last search launch's `waves` wavefronts into
+// the result slots, the histogram and the control block's counters.
+hipError_t launch_exit_fold(const SearchParams& sp, uint32_t waves, hipStream_t s);
 hipError_t search_occupancy(uint32_t max_w32, uint32_t rule, uint32_t waves_per_block, uint32_t lds_bytes,
                             int* blocks_per_cu);
 

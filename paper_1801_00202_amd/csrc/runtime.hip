@@ -376,7 +376,7 @@ struct mce_graph_s {
     uint64_t in_words = 0, adj_words = 0, ord_words = 0, hist_total = 0;
     DevBuf d_desc, d_in, d_adj, d_order, d_nbr;
     // workspace of the solve
-    DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_params, d_sub;
+    DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_exit, d_params, d_sub;
     HostPinned h_params; // staging of the search parameters of direct (not replayed) solves
     // parameter block of the captured graph: written once, before the capture,
     // and read by every replay; no other solve touches it
@@ -546,10 +546,10 @@ int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c);
 int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
 {
     const void* before[] = {h->d_results.p, h->d_hist.p, h->d_ctl.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
-                            h->d_spill.p, h->d_state.p, h->h_out.p};
+                            h->d_spill.p, h->d_state.p, h->d_exit.p, h->h_out.p};
     const int rc = ensure_workspace_bufs(h, c);
     const void* after[] = {h->d_results.p, h->d_hist.p, h->d_ctl.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
-                           h->d_spill.p, h->d_state.p, h->h_out.p};
+                           h->d_spill.p, h->d_state.p, h->d_exit.p, h->h_out.p};
     if (std::memcmp(before, after, sizeof(before)) != 0) h->ws_gen++;
     return rc;
 }
@@ -567,6 +567,7 @@ int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c)
     const uint64_t spill = 4ull * spill_frame_words(c.w32cap) * c.spill_levels * c.spill_chunks;
     if ((rc = h->d_spill.ensure(spill)) != MCE_OK) return rc;
     if ((rc = h->d_state.ensure(4ull * c.blocks * c.wpb)) != MCE_OK) return rc;
+    if ((rc = h->d_exit.ensure(sizeof(WaveExit) * c.blocks * c.wpb)) != MCE_OK) return rc;
     if ((rc = h->d_params.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
     if ((rc = h->h_params.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
     if ((rc = h->h_out.ensure(out_bytes(h))) != MCE_OK) return rc;
@@ -590,6 +591,7 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c, bool local = false)
     sp.num_wg = c.blocks;
     sp.spill = h->d_spill.as<uint32_t>();
     sp.wave_state = h->d_state.as<uint32_t>();
+    sp.exits = h->d_exit.as<WaveExit>();
     sp.rec_words = kRecHeader + 4 * c.w32cap;
     sp.w32cap = c.w32cap;
     sp.slot_words = c.slot_words;
@@ -640,6 +642,7 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
     HIP_TRY(launch_search(sp, d_sp, local ? h->lmax_w32 : h->max_w32, c.blocks, c.wpb, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
+    HIP_TRY(launch_exit_fold(sp, c.blocks * c.wpb, s));
     char* out = static_cast<char*>(h->h_out.p);
     HIP_TRY(hipMemcpyAsync(out, sp.results, sizeof(DevResult) * h->num_graphs, hipMemcpyDeviceToHost, s));
     out += sizeof(DevResult) * h->num_graphs;
@@ -787,7 +790,7 @@ int fit_fixed_workspace(mce_graph_s* h, LaunchCfg* c, uint32_t floor)
     while (2ull * cap <= recs && 2ull * cap <= c->cap) cap *= 2;
     c->cap = cap;
     const uint64_t wg_max = std::min<uint64_t>(h->d_mail.bytes / sizeof(Mailbox), h->d_mail_rec.bytes / rec_bytes);
-    const uint64_t waves_max = h->d_state.bytes / 4;
+    const uint64_t waves_max = std::min<uint64_t>(h->d_state.bytes / 4, h->d_exit.bytes / sizeof(WaveExit));
     const uint64_t chunk_bytes = 4ull * spill_frame_words(c->w32cap) * c->spill_levels;
     const uint64_t chunks_fit = h->d_spill.bytes / chunk_bytes;
     if (chunks_fit == 0 || wg_max == 0) return MCE_E_NOMEM;
@@ -1566,8 +1569,9 @@ namespace {
 constexpr int kNoAllocDevices = 64;
 // Fixed parts of the scratch area (the rest is the spill pool): a pool of
 // root units, mailboxes and record slots for up to kNoAllocWorkgroups search
-// workgroups, and states for up to kNoAllocWaves wavefronts.  Records are
-// sized for the widest layout the entry point takes (w32 = 64).
+// workgroups, and states and exit records for up to kNoAllocWaves wavefronts
+// (10 MiB of the area).  Unit records are sized for the widest layout the
+// entry point takes (w32 = 64).
 constexpr uint32_t kNoAllocW32 = (MCE_NOALLOC_MAX_N + 31u) / 32u;
 constexpr uint32_t kNoAllocRecords = 8192, kNoAllocWorkgroups = 1024, kNoAllocWaves = 16384;
 
@@ -1617,6 +1621,7 @@ int noalloc_setup(NoAllocCtx& x, int dev)
     take(h->d_mail, sizeof(Mailbox) * kNoAllocWorkgroups);
     take(h->d_mail_rec, rec_bytes * kNoAllocWorkgroups);
     take(h->d_state, 4ull * kNoAllocWaves);
+    take(h->d_exit, sizeof(WaveExit) * kNoAllocWaves);
     if (off >= MCE_NOALLOC_SCRATCH_BYTES) return MCE_E_NOMEM;
     h->d_spill.borrow(x.base + off, MCE_NOALLOC_SCRATCH_BYTES - off);
     x.host_out.assign(sizeof(DevResult) + sizeof(QueueCtl) + 8ull * (MCE_NOALLOC_MAX_N + 1), 0);
