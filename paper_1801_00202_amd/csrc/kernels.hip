@@ -2855,12 +2855,15 @@ __global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(Search
     set_state(kWaveExited);
 }
 
-// One thread per exit record, 256 a workgroup.  The counters are summed over
-// the workgroup and added to the control block once; when all records of the
+// 256 exit records a workgroup of 1024 threads: thread t < 256 takes record
+// t's totals and counters; for the histogram, each of the 16 wavefronts adds
+// 16 records' entries (lane i: entry i).  The counters are summed over the
+// workgroup and added to the control block once; when all records of the
 // workgroup that hold totals report to the same result slot and histogram
 // (one graph, as in every search of local graphs), so are the totals, else each
-// record adds its own.
-constexpr uint32_t kFoldThreads = 256;
+// record adds its own.  Record indices are clamped instead of branched on, so
+// that the loads of a thread are independent and leave back to back.
+constexpr uint32_t kFoldThreads = 1024, kFoldRecs = 256;
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 {
 #pragma unroll
@@ -2882,100 +2885,123 @@ __device__ __forceinline__ uint32_t wave_max32(uint32_t v)
 
 __global__ void __launch_bounds__(kFoldThreads) exit_fold_kernel(SearchParams sp, uint32_t waves)
 {
-    constexpr uint32_t NW = kFoldThreads / 64;
+    constexpr uint32_t NW = kFoldThreads / 64, FW = kFoldRecs / 64; // wavefronts; those holding records
+    constexpr uint32_t HR = kFoldRecs / NW;                           // histogram records a wavefront
     constexpr uint32_t kSums = 14; // 10 counters, then count, nodes, children, hash_sum
-    __shared__ unsigned long long part[NW][kSums + 2];
+    __shared__ unsigned long long part[FW][kSums + 2];
     __shared__ unsigned long long hpart[NW][kHistLds];
     __shared__ unsigned long long hoff_min, hoff_max;
     __shared__ uint32_t res_min, res_max;
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
-    const uint32_t base = blockIdx.x * kFoldThreads;
-    const uint32_t r = base + t;
-    const bool have = r < waves;
-    const WaveExit* e = sp.exits + (have ? r : 0u);
+    const uint32_t base = blockIdx.x * kFoldRecs;
+    const uint32_t last = waves - 1u;
     if (t == 0) {
         res_min = kNoSlot;
         res_max = 0u;
         hoff_min = ~0ull;
         hoff_max = 0ull;
     }
-    __syncthreads();
-    const uint32_t res = have ? e->res : kNoSlot;
-    const bool holds = res != kNoSlot;
-    const unsigned long long hoff = holds ? e->hist_off : 0ull;
-    if (holds) {
-        atomicMin(&res_min, res);
-        atomicMax(&res_max, res);
-        atomicMin(&hoff_min, hoff);
-        atomicMax(&hoff_max, hoff);
+    // histogram entries first: they are independent of the rest
+    unsigned long long h = 0ull;
+    {
+        const uint32_t r0 = base + wv * HR;
+        unsigned long long x[HR];
+#pragma unroll
+        for (uint32_t k = 0; k < HR; k++) x[k] = sp.exits[umin32(r0 + k, last)].hist[lane];
+#pragma unroll
+        for (uint32_t k = 0; k < HR; k++) h += r0 + k <= last ? x[k] : 0ull;
     }
+    const uint32_t r = base + t;
+    const bool have = wv < FW && r <= last;
+    const WaveExit* e = sp.exits + umin32(r, last);
     unsigned long long v[kSums];
-    v[0] = have ? e->units : 0ull;
-    v[1] = have ? e->donations : 0ull;
-    v[2] = have ? e->spills : 0ull;
-    v[3] = have ? e->checks : 0ull;
-    v[4] = have ? e->flushes : 0ull;
-    v[5] = have ? e->busy : 0ull;
-    v[6] = have ? e->run : 0ull;
-    v[7] = have ? e->ramp : 0ull;
-    v[8] = have ? e->tail : 0ull;
-    v[9] = 0ull;
-    v[10] = holds ? e->count : 0ull;
-    v[11] = holds ? e->nodes : 0ull;
-    v[12] = holds ? e->children : 0ull;
-    v[13] = holds ? e->hash_sum : 0ull;
-    const unsigned long long hx = holds ? e->hash_xor : 0ull;
-    const uint32_t om = holds ? e->omega : 0u;
+    uint32_t res = kNoSlot, om = 0u;
+    unsigned long long hoff = 0ull, hx = 0ull;
+    if (wv < FW) {
+        const uint32_t er = e->res;
+        res = have ? er : kNoSlot;
+        om = e->omega;
+        hoff = e->hist_off;
+        hx = e->hash_xor;
+        v[0] = e->units;
+        v[1] = e->donations;
+        v[2] = e->spills;
+        v[3] = e->checks;
+        v[4] = e->flushes;
+        v[5] = e->busy;
+        v[6] = e->run;
+        v[7] = e->ramp;
+        v[8] = e->tail;
+        v[9] = 0ull;
+        v[10] = e->count;
+        v[11] = e->nodes;
+        v[12] = e->children;
+        v[13] = e->hash_sum;
+    }
+    const bool holds = res != kNoSlot;
+    __syncthreads();
+    if (wv < FW) {
+        // the slot and histogram range of the wavefront's holding records, then
+        // one LDS atomic a wavefront
+        uint32_t rmin = res, rmax = holds ? res : 0u;
+        unsigned long long omin = holds ? hoff : ~0ull, omax = holds ? hoff : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            rmin = umin32(rmin, (uint32_t)__shfl_xor((int)rmin, o, 64));
+            rmax = umax32(rmax, (uint32_t)__shfl_xor((int)rmax, o, 64));
+            const unsigned long long a = __shfl_xor(omin, o, 64), b = __shfl_xor(omax, o, 64);
+            omin = a < omin ? a : omin;
+            omax = b > omax ? b : omax;
+        }
+        if (lane == 0 && rmin != kNoSlot) {
+            atomicMin(&res_min, rmin);
+            atomicMax(&res_max, rmax);
+            atomicMin(&hoff_min, omin);
+            atomicMax(&hoff_max, omax);
+        }
+    }
+    hpart[wv][lane] = h;
     __syncthreads();
     const bool one_slot = res_min != kNoSlot && res_min == res_max && hoff_min == hoff_max;
-    const uint32_t nsum = one_slot ? kSums : 10u;
+    if (wv < FW) {
 #pragma unroll
-    for (uint32_t k = 0; k < kSums; k++)
-        if (k < nsum) {
-            const unsigned long long w = wave_sum64(v[k]);
+        for (uint32_t k = 0; k < 10u; k++) {
+            const unsigned long long w = wave_sum64(have ? v[k] : 0ull);
             if (lane == 0) part[wv][k] = w;
         }
-    if (one_slot) {
-        const unsigned long long wx = wave_xor64(hx);
-        const uint32_t wm = wave_max32(om);
-        if (lane == 0) {
-            part[wv][kSums] = wx;
-            part[wv][kSums + 1] = wm;
-        }
-        // histogram: lane i adds entry i of the wavefront's 64 records (the
-        // index is clamped instead of branched on, so that the loads are
-        // independent and leave back to back)
-        unsigned long long h = 0ull;
-        const uint32_t r0 = base + wv * 64u;
-#pragma unroll 16
-        for (uint32_t k = 0; k < 64u; k++) {
-            const uint32_t rr = r0 + k;
-            const unsigned long long x = sp.exits[rr < waves ? rr : waves - 1u].hist[lane];
-            h += rr < waves ? x : 0ull;
-        }
-        hpart[wv][lane] = h;
-    } else if (holds) {
-        DevResult* d = sp.results + res;
-        if (v[10]) atomicAdd(&d->count, v[10]);
-        if (v[11]) atomicAdd(&d->nodes, v[11]);
-        if (v[12]) atomicAdd(&d->children, v[12]);
-        if (v[13]) atomicAdd(&d->hash_sum, v[13]);
-        if (hx) atomicXor(&d->hash_xor, hx);
-        if (om) atomicMax(&d->omega, om);
-        for (uint32_t i = 0; i < kHistLds; i++) {
-            const unsigned long long hv = e->hist[i];
-            if (hv) atomicAdd(&sp.hist[hoff + i], hv);
+        if (one_slot) {
+#pragma unroll
+            for (uint32_t k = 10; k < kSums; k++) {
+                const unsigned long long w = wave_sum64(holds ? v[k] : 0ull);
+                if (lane == 0) part[wv][k] = w;
+            }
+            const unsigned long long wx = wave_xor64(holds ? hx : 0ull);
+            const uint32_t wm = wave_max32(holds ? om : 0u);
+            if (lane == 0) {
+                part[wv][kSums] = wx;
+                part[wv][kSums + 1] = wm;
+            }
+        } else if (holds) {
+            DevResult* d = sp.results + res;
+            if (v[10]) atomicAdd(&d->count, v[10]);
+            if (v[11]) atomicAdd(&d->nodes, v[11]);
+            if (v[12]) atomicAdd(&d->children, v[12]);
+            if (v[13]) atomicAdd(&d->hash_sum, v[13]);
+            if (hx) atomicXor(&d->hash_xor, hx);
+            if (om) atomicMax(&d->omega, om);
+            for (uint32_t i = 0; i < kHistLds; i++) {
+                const unsigned long long hv = e->hist[i];
+                if (hv) atomicAdd(&sp.hist[hoff + i], hv);
+            }
         }
     }
     __syncthreads();
-    if (t < kSums + 2u) {
+    if (t < kSums + 2u && (t < 10u || one_slot)) {
         unsigned long long w = 0ull;
-        if (t < nsum || (one_slot && t < kSums + 2u)) {
 #pragma unroll
-            for (uint32_t q = 0; q < NW; q++) {
-                const unsigned long long pq = part[q][t];
-                w = t == kSums ? (w ^ pq) : t == kSums + 1u ? (pq > w ? pq : w) : w + pq;
-            }
+        for (uint32_t q = 0; q < FW; q++) {
+            const unsigned long long pq = part[q][t];
+            w = t == kSums ? (w ^ pq) : t == kSums + 1u ? (pq > w ? pq : w) : w + pq;
         }
         if (w != 0ull) {
             QueueCtl* c = sp.ctl;
@@ -3001,10 +3027,10 @@ __global__ void __launch_bounds__(kFoldThreads) exit_fold_kernel(SearchParams sp
         }
     }
     if (one_slot && wv == 0) {
-        unsigned long long h = 0ull;
+        unsigned long long hs = 0ull;
 #pragma unroll
-        for (uint32_t q = 0; q < NW; q++) h += hpart[q][lane];
-        if (h) atomicAdd(&sp.hist[hoff_min + lane], h);
+        for (uint32_t q = 0; q < NW; q++) hs += hpart[q][lane];
+        if (hs) atomicAdd(&sp.hist[hoff_min + lane], hs);
     }
 }
 
@@ -3347,8 +3373,8 @@ hipError_t launch_exit_fold(const SearchParams& sp, uint32_t waves, hipStream_t 
 {
     (void)hipGetLastError(); // report only this call's launch errors
     if (waves == 0) return hipSuccess;
-    hipLaunchKernelGGL(exit_fold_kernel, dim3((waves + kFoldThreads - 1u) / kFoldThreads), dim3(kFoldThreads), 0, s,
-                       sp, waves);
+    hipLaunchKernelGGL(exit_fold_kernel, dim3((waves + kFoldRecs - 1u) / kFoldRecs), dim3(kFoldThreads), 0, s, sp,
+                       waves);
     return hipGetLastError();
 }
 
