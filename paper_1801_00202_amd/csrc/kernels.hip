@@ -1750,14 +1750,32 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
 
 // The wavefront's exit record (WaveExit): its unfolded totals of graph ctx->g
 // and its counters, written with plain stores; exit_fold_kernel adds the
-// records up after the launch.  `first` and `last` are lane 0's wall-clock
-// ticks of its first unit start and last unit end (0: no unit).
+// records up after the launch.  Without exit records (SearchParams.exits
+// null) the wavefront adds them itself with device atomics.  `first` and
+// `last` are lane 0's wall-clock ticks of its first unit start and last unit
+// end (0: no unit).
 __device__ __attribute__((noinline)) void cold_exit(const SearchParams* __restrict__ spp, uint32_t* wl,
                                                     uint32_t gwave, uint64_t t_start, uint64_t first, uint64_t last)
 {
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
-    const WaveCtx* ctx = wave_ctx(wl);
+    WaveCtx* ctx = wave_ctx(wl);
+    if (sp.exits == nullptr) {
+        cold_fold(spp, wl);
+        if (lane == 0) {
+            if (ctx->units) atomicAdd(&sp.ctl->units, ctx->units);
+            if (ctx->donations) atomicAdd(&sp.ctl->donations, ctx->donations);
+            if (ctx->spills) atomicAdd(&sp.ctl->spill_levels_written, ctx->spills);
+            if (ctx->checks) atomicAdd(&sp.ctl->checks, (unsigned long long)ctx->checks);
+            if (ctx->flushes) atomicAdd(&sp.ctl->flushes, (unsigned long long)ctx->flushes);
+            const uint64_t t_exit = wall_clock64();
+            atomicAdd(&sp.ctl->busy_ticks, ctx->busy);
+            atomicAdd(&sp.ctl->run_ticks, (unsigned long long)(t_exit - t_start));
+            atomicAdd(&sp.ctl->ramp_ticks, (unsigned long long)((first ? first : t_exit) - t_start));
+            atomicAdd(&sp.ctl->tail_ticks, (unsigned long long)(first ? t_exit - last : 0));
+        }
+        return;
+    }
     WaveExit* e = sp.exits + gwave;
     const uint32_t g = bcast0(ctx->g);
     e->hist[lane] = reinterpret_cast<const unsigned long long*>(wl + kOffHist)[lane];
