@@ -1750,32 +1750,14 @@ __device__ __attribute__((noinline)) void cold_fold(const SearchParams* __restri
 
 // The wavefront's exit record (WaveExit): its unfolded totals of graph ctx->g
 // and its counters, written with plain stores; exit_fold_kernel adds the
-// records up after the launch.  Without exit records (SearchParams.exits
-// null) the wavefront adds them itself with device atomics.  `first` and
-// `last` are lane 0's wall-clock ticks of its first unit start and last unit
-// end (0: no unit).
+// records up after the launch.  `first` and `last` are lane 0's wall-clock
+// ticks of its first unit start and last unit end (0: no unit).
 __device__ __attribute__((noinline)) void cold_exit(const SearchParams* __restrict__ spp, uint32_t* wl,
                                                     uint32_t gwave, uint64_t t_start, uint64_t first, uint64_t last)
 {
     const SearchParams& sp = *spp;
     const uint32_t lane = lane_id();
-    WaveCtx* ctx = wave_ctx(wl);
-    if (sp.exits == nullptr) {
-        cold_fold(spp, wl);
-        if (lane == 0) {
-            if (ctx->units) atomicAdd(&sp.ctl->units, ctx->units);
-            if (ctx->donations) atomicAdd(&sp.ctl->donations, ctx->donations);
-            if (ctx->spills) atomicAdd(&sp.ctl->spill_levels_written, ctx->spills);
-            if (ctx->checks) atomicAdd(&sp.ctl->checks, (unsigned long long)ctx->checks);
-            if (ctx->flushes) atomicAdd(&sp.ctl->flushes, (unsigned long long)ctx->flushes);
-            const uint64_t t_exit = wall_clock64();
-            atomicAdd(&sp.ctl->busy_ticks, ctx->busy);
-            atomicAdd(&sp.ctl->run_ticks, (unsigned long long)(t_exit - t_start));
-            atomicAdd(&sp.ctl->ramp_ticks, (unsigned long long)((first ? first : t_exit) - t_start));
-            atomicAdd(&sp.ctl->tail_ticks, (unsigned long long)(first ? t_exit - last : 0));
-        }
-        return;
-    }
+    const WaveCtx* ctx = wave_ctx(wl);
     WaveExit* e = sp.exits + gwave;
     const uint32_t g = bcast0(ctx->g);
     e->hist[lane] = reinterpret_cast<const unsigned long long*>(wl + kOffHist)[lane];
@@ -2873,15 +2855,16 @@ __global__ void __launch_bounds__(64 * max_search_wpb(WPL)) search_kernel(Search
     set_state(kWaveExited);
 }
 
-// 256 exit records a workgroup of 1024 threads: thread t < 256 takes record
-// t's totals and counters; for the histogram, each of the 16 wavefronts adds
-// 16 records' entries (lane i: entry i).  The counters are summed over the
-// workgroup and added to the control block once; when all records of the
-// workgroup that hold totals report to the same result slot and histogram
-// (one graph, as in every search of local graphs), so are the totals, else each
-// record adds its own.  Record indices are clamped instead of branched on, so
-// that the loads of a thread are independent and leave back to back.
-constexpr uint32_t kFoldThreads = 1024, kFoldRecs = 256;
+// One wavefront a workgroup, no LDS (so that a fold can start beside other
+// work that holds most of a compute unit), kFoldRecs exit records a
+// wavefront: lane r < kFoldRecs takes record r's totals and counters, lane i
+// adds histogram entry i of all of them.  The counters are summed over the
+// wavefront and added to the control block once; when all records that hold
+// totals report to the same result slot and histogram (one graph, as in
+// every search of local graphs), so are the totals, else each record adds
+// its own.  Record indices are clamped instead of branched on, so that a
+// lane's loads are independent and leave back to back.
+constexpr uint32_t kFoldRecs = 32;
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 {
 #pragma unroll
@@ -2900,156 +2883,122 @@ __device__ __forceinline__ uint32_t wave_max32(uint32_t v)
     for (int o = 32; o > 0; o >>= 1) v = umax32(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
 }
-
-__global__ void __launch_bounds__(kFoldThreads) exit_fold_kernel(SearchParams sp, uint32_t waves)
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v)
 {
-    constexpr uint32_t NW = kFoldThreads / 64, FW = kFoldRecs / 64; // wavefronts; those holding records
-    constexpr uint32_t HR = kFoldRecs / NW;                           // histogram records a wavefront
-    constexpr uint32_t kSums = 14; // 10 counters, then count, nodes, children, hash_sum
-    __shared__ unsigned long long part[FW][kSums + 2];
-    __shared__ unsigned long long hpart[NW][kHistLds];
-    __shared__ unsigned long long hoff_min, hoff_max;
-    __shared__ uint32_t res_min, res_max;
-    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = umin32(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long a = __shfl_xor(v, o, 64);
+        v = a < v ? a : v;
+    }
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long a = __shfl_xor(v, o, 64);
+        v = a > v ? a : v;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(64) exit_fold_kernel(SearchParams sp, uint32_t waves)
+{
+    const uint32_t lane = threadIdx.x;
     const uint32_t base = blockIdx.x * kFoldRecs;
     const uint32_t last = waves - 1u;
-    if (t == 0) {
-        res_min = kNoSlot;
-        res_max = 0u;
-        hoff_min = ~0ull;
-        hoff_max = 0ull;
-    }
     // histogram entries first: they are independent of the rest
     unsigned long long h = 0ull;
     {
-        const uint32_t r0 = base + wv * HR;
-        unsigned long long x[HR];
+        unsigned long long x[kFoldRecs];
 #pragma unroll
-        for (uint32_t k = 0; k < HR; k++) x[k] = sp.exits[umin32(r0 + k, last)].hist[lane];
+        for (uint32_t k = 0; k < kFoldRecs; k++) x[k] = sp.exits[umin32(base + k, last)].hist[lane];
 #pragma unroll
-        for (uint32_t k = 0; k < HR; k++) h += r0 + k <= last ? x[k] : 0ull;
+        for (uint32_t k = 0; k < kFoldRecs; k++) h += base + k <= last ? x[k] : 0ull;
     }
-    const uint32_t r = base + t;
-    const bool have = wv < FW && r <= last;
+    const uint32_t r = base + lane;
+    const bool have = lane < kFoldRecs && r <= last;
     const WaveExit* e = sp.exits + umin32(r, last);
-    unsigned long long v[kSums];
-    uint32_t res = kNoSlot, om = 0u;
-    unsigned long long hoff = 0ull, hx = 0ull;
-    if (wv < FW) {
-        const uint32_t er = e->res;
-        res = have ? er : kNoSlot;
-        om = e->omega;
-        hoff = e->hist_off;
-        hx = e->hash_xor;
-        v[0] = e->units;
-        v[1] = e->donations;
-        v[2] = e->spills;
-        v[3] = e->checks;
-        v[4] = e->flushes;
-        v[5] = e->busy;
-        v[6] = e->run;
-        v[7] = e->ramp;
-        v[8] = e->tail;
-        v[9] = 0ull;
-        v[10] = e->count;
-        v[11] = e->nodes;
-        v[12] = e->children;
-        v[13] = e->hash_sum;
-    }
+    const uint32_t er = e->res;
+    const uint32_t res = have ? er : kNoSlot;
     const bool holds = res != kNoSlot;
-    __syncthreads();
-    if (wv < FW) {
-        // the slot and histogram range of the wavefront's holding records, then
-        // one LDS atomic a wavefront
-        uint32_t rmin = res, rmax = holds ? res : 0u;
-        unsigned long long omin = holds ? hoff : ~0ull, omax = holds ? hoff : 0ull;
+    const unsigned long long hoff = e->hist_off, hx = e->hash_xor;
+    const uint32_t om = e->omega;
+    unsigned long long v[14];
+    v[0] = e->units;
+    v[1] = e->donations;
+    v[2] = e->spills;
+    v[3] = e->checks;
+    v[4] = e->flushes;
+    v[5] = e->busy;
+    v[6] = e->run;
+    v[7] = e->ramp;
+    v[8] = e->tail;
+    v[9] = 0ull;
+    v[10] = e->count;
+    v[11] = e->nodes;
+    v[12] = e->children;
+    v[13] = e->hash_sum;
+    const uint32_t rmin = wave_min32(res), rmax = wave_max32(holds ? res : 0u);
+    const unsigned long long omin = wave_min64(holds ? hoff : ~0ull), omax = wave_max64(holds ? hoff : 0ull);
+    const bool one_slot = rmin != kNoSlot && rmin == rmax && omin == omax;
+    // lane k ends with sum k (k < 14), the XOR (14) or the maximum (15)
+    unsigned long long mine = 0ull;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            rmin = umin32(rmin, (uint32_t)__shfl_xor((int)rmin, o, 64));
-            rmax = umax32(rmax, (uint32_t)__shfl_xor((int)rmax, o, 64));
-            const unsigned long long a = __shfl_xor(omin, o, 64), b = __shfl_xor(omax, o, 64);
-            omin = a < omin ? a : omin;
-            omax = b > omax ? b : omax;
-        }
-        if (lane == 0 && rmin != kNoSlot) {
-            atomicMin(&res_min, rmin);
-            atomicMax(&res_max, rmax);
-            atomicMin(&hoff_min, omin);
-            atomicMax(&hoff_max, omax);
+    for (uint32_t k = 0; k < 14u; k++) {
+        const bool counter = k < 10u;
+        if (counter || one_slot) {
+            const unsigned long long w = wave_sum64(counter ? (have ? v[k] : 0ull) : (holds ? v[k] : 0ull));
+            if (lane == k) mine = w;
         }
     }
-    hpart[wv][lane] = h;
-    __syncthreads();
-    const bool one_slot = res_min != kNoSlot && res_min == res_max && hoff_min == hoff_max;
-    if (wv < FW) {
-#pragma unroll
-        for (uint32_t k = 0; k < 10u; k++) {
-            const unsigned long long w = wave_sum64(have ? v[k] : 0ull);
-            if (lane == 0) part[wv][k] = w;
-        }
-        if (one_slot) {
-#pragma unroll
-            for (uint32_t k = 10; k < kSums; k++) {
-                const unsigned long long w = wave_sum64(holds ? v[k] : 0ull);
-                if (lane == 0) part[wv][k] = w;
-            }
-            const unsigned long long wx = wave_xor64(holds ? hx : 0ull);
-            const uint32_t wm = wave_max32(holds ? om : 0u);
-            if (lane == 0) {
-                part[wv][kSums] = wx;
-                part[wv][kSums + 1] = wm;
-            }
-        } else if (holds) {
-            DevResult* d = sp.results + res;
-            if (v[10]) atomicAdd(&d->count, v[10]);
-            if (v[11]) atomicAdd(&d->nodes, v[11]);
-            if (v[12]) atomicAdd(&d->children, v[12]);
-            if (v[13]) atomicAdd(&d->hash_sum, v[13]);
-            if (hx) atomicXor(&d->hash_xor, hx);
-            if (om) atomicMax(&d->omega, om);
-            for (uint32_t i = 0; i < kHistLds; i++) {
-                const unsigned long long hv = e->hist[i];
-                if (hv) atomicAdd(&sp.hist[hoff + i], hv);
-            }
+    if (one_slot) {
+        const unsigned long long wx = wave_xor64(holds ? hx : 0ull);
+        const uint32_t wm = wave_max32(holds ? om : 0u);
+        if (lane == 14u) mine = wx;
+        if (lane == 15u) mine = wm;
+    } else if (holds) {
+        DevResult* d = sp.results + res;
+        if (v[10]) atomicAdd(&d->count, v[10]);
+        if (v[11]) atomicAdd(&d->nodes, v[11]);
+        if (v[12]) atomicAdd(&d->children, v[12]);
+        if (v[13]) atomicAdd(&d->hash_sum, v[13]);
+        if (hx) atomicXor(&d->hash_xor, hx);
+        if (om) atomicMax(&d->omega, om);
+        for (uint32_t i = 0; i < kHistLds; i++) {
+            const unsigned long long hv = e->hist[i];
+            if (hv) atomicAdd(&sp.hist[hoff + i], hv);
         }
     }
-    __syncthreads();
-    if (t < kSums + 2u && (t < 10u || one_slot)) {
-        unsigned long long w = 0ull;
-#pragma unroll
-        for (uint32_t q = 0; q < FW; q++) {
-            const unsigned long long pq = part[q][t];
-            w = t == kSums ? (w ^ pq) : t == kSums + 1u ? (pq > w ? pq : w) : w + pq;
-        }
-        if (w != 0ull) {
-            QueueCtl* c = sp.ctl;
-            DevResult* d = sp.results + (one_slot ? res_min : 0u);
-            switch (t) {
-            case 0: atomicAdd(&c->units, w); break;
-            case 1: atomicAdd(&c->donations, w); break;
-            case 2: atomicAdd(&c->spill_levels_written, w); break;
-            case 3: atomicAdd(&c->checks, w); break;
-            case 4: atomicAdd(&c->flushes, w); break;
-            case 5: atomicAdd(&c->busy_ticks, w); break;
-            case 6: atomicAdd(&c->run_ticks, w); break;
-            case 7: atomicAdd(&c->ramp_ticks, w); break;
-            case 8: atomicAdd(&c->tail_ticks, w); break;
-            case 10: atomicAdd(&d->count, w); break;
-            case 11: atomicAdd(&d->nodes, w); break;
-            case 12: atomicAdd(&d->children, w); break;
-            case 13: atomicAdd(&d->hash_sum, w); break;
-            case kSums: atomicXor(&d->hash_xor, w); break;
-            case kSums + 1: atomicMax(&d->omega, (uint32_t)w); break;
-            default: break;
-            }
+    if (mine != 0ull) {
+        QueueCtl* c = sp.ctl;
+        DevResult* d = sp.results + (one_slot ? rmin : 0u);
+        switch (lane) {
+        case 0: atomicAdd(&c->units, mine); break;
+        case 1: atomicAdd(&c->donations, mine); break;
+        case 2: atomicAdd(&c->spill_levels_written, mine); break;
+        case 3: atomicAdd(&c->checks, mine); break;
+        case 4: atomicAdd(&c->flushes, mine); break;
+        case 5: atomicAdd(&c->busy_ticks, mine); break;
+        case 6: atomicAdd(&c->run_ticks, mine); break;
+        case 7: atomicAdd(&c->ramp_ticks, mine); break;
+        case 8: atomicAdd(&c->tail_ticks, mine); break;
+        case 10: atomicAdd(&d->count, mine); break;
+        case 11: atomicAdd(&d->nodes, mine); break;
+        case 12: atomicAdd(&d->children, mine); break;
+        case 13: atomicAdd(&d->hash_sum, mine); break;
+        case 14: atomicXor(&d->hash_xor, mine); break;
+        case 15: atomicMax(&d->omega, (uint32_t)mine); break;
+        default: break;
         }
     }
-    if (one_slot && wv == 0) {
-        unsigned long long hs = 0ull;
-#pragma unroll
-        for (uint32_t q = 0; q < NW; q++) hs += hpart[q][lane];
-        if (hs) atomicAdd(&sp.hist[hoff_min + lane], hs);
-    }
+    if (one_slot && h) atomicAdd(&sp.hist[omin + lane], h);
 }
 
 } // namespace
@@ -3391,8 +3340,7 @@ hipError_t launch_exit_fold(const SearchParams& sp, uint32_t waves, hipStream_t 
 {
     (void)hipGetLastError(); // report only this call's launch errors
     if (waves == 0) return hipSuccess;
-    hipLaunchKernelGGL(exit_fold_kernel, dim3((waves + kFoldRecs - 1u) / kFoldRecs), dim3(kFoldThreads), 0, s, sp,
-                       waves);
+    hipLaunchKernelGGL(exit_fold_kernel, dim3((waves + kFoldRecs - 1u) / kFoldRecs), dim3(64), 0, s, sp, waves);
     return hipGetLastError();
 }
 

@@ -176,8 +176,7 @@ struct SearchParams {
     uint32_t refresh_children; // children a workgroup processes between two looks at its mailbox
     uint32_t poll_iters;       // idle iterations between two looks at the end-of-search counter
     uint32_t* wave_state;     // per wavefront: kWave* phase (for deadline reports), or null
-    WaveExit* exits;          // per wavefront (blockIdx.x * waves per workgroup + wavefront), or null:
-                              // each wavefront adds its totals with atomics as it leaves
+    WaveExit* exits;          // per wavefront (blockIdx.x * waves per workgroup + wavefront)
     uint32_t pivot_rule;      // kPivot*
     uint32_t pad0;
     // host-written word in coherent pinned host memory, or null: non-zero asks

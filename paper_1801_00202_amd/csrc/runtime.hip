@@ -642,7 +642,7 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
     HIP_TRY(launch_search(sp, d_sp, local ? h->lmax_w32 : h->max_w32, c.blocks, c.wpb, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
-    if (sp.exits) HIP_TRY(launch_exit_fold(sp, c.blocks * c.wpb, s));
+    HIP_TRY(launch_exit_fold(sp, c.blocks * c.wpb, s));
     char* out = static_cast<char*>(h->h_out.p);
     HIP_TRY(hipMemcpyAsync(out, sp.results, sizeof(DevResult) * h->num_graphs, hipMemcpyDeviceToHost, s));
     out += sizeof(DevResult) * h->num_graphs;
@@ -836,11 +836,6 @@ int run_solve(mce_graph_t g, uint64_t first, uint64_t last, mce_result_t* res, h
         if ((rc = ensure_workspace(g, c)) != MCE_OK) return rc;
         SearchParams sp = make_params(g, c, local);
         sp.cancel = cancel;
-        // A served job shares the device with other jobs' persistent search
-        // workgroups: a fold kernel after its search would wait for a compute
-        // unit with room behind them (serving mix: 5% less capacity, 15% more
-        // latency at 0.8 load), so its wavefronts add their totals themselves.
-        if (cancel) sp.exits = nullptr;
         if (lds_bytes_out) *lds_bytes_out = search_lds_bytes(c.wave_lds_words, kRecHeader + 4 * c.w32cap, c.wpb) * c.blocks;
         const bool enumerate = verts != nullptr || offs != nullptr;
         if (enumerate) {
