@@ -2914,14 +2914,11 @@ __global__ void __launch_bounds__(64) exit_fold_kernel(SearchParams sp, uint32_t
     const uint32_t base = blockIdx.x * kFoldRecs;
     const uint32_t last = waves - 1u;
     // histogram entries first: they are independent of the rest
-    unsigned long long h = 0ull;
-    {
-        unsigned long long x[kFoldRecs];
+    unsigned long long x[kFoldRecs], h = 0ull;
 #pragma unroll
-        for (uint32_t k = 0; k < kFoldRecs; k++) x[k] = sp.exits[umin32(base + k, last)].hist[lane];
+    for (uint32_t k = 0; k < kFoldRecs; k++) x[k] = sp.exits[umin32(base + k, last)].hist[lane];
 #pragma unroll
-        for (uint32_t k = 0; k < kFoldRecs; k++) h += base + k <= last ? x[k] : 0ull;
-    }
+    for (uint32_t k = 0; k < kFoldRecs; k++) h += base + k <= last ? x[k] : 0ull;
     const uint32_t r = base + lane;
     const bool have = lane < kFoldRecs && r <= last;
     const WaveExit* e = sp.exits + umin32(r, last);
@@ -2963,17 +2960,23 @@ __global__ void __launch_bounds__(64) exit_fold_kernel(SearchParams sp, uint32_t
         const uint32_t wm = wave_max32(holds ? om : 0u);
         if (lane == 14u) mine = wx;
         if (lane == 15u) mine = wm;
-    } else if (holds) {
-        DevResult* d = sp.results + res;
-        if (v[10]) atomicAdd(&d->count, v[10]);
-        if (v[11]) atomicAdd(&d->nodes, v[11]);
-        if (v[12]) atomicAdd(&d->children, v[12]);
-        if (v[13]) atomicAdd(&d->hash_sum, v[13]);
-        if (hx) atomicXor(&d->hash_xor, hx);
-        if (om) atomicMax(&d->omega, om);
-        for (uint32_t i = 0; i < kHistLds; i++) {
-            const unsigned long long hv = e->hist[i];
-            if (hv) atomicAdd(&sp.hist[hoff + i], hv);
+    } else {
+        // each record adds its own: lane r its totals, lane i entry i of
+        // every record's histogram (the entries loaded above)
+        if (holds) {
+            DevResult* d = sp.results + res;
+            if (v[10]) atomicAdd(&d->count, v[10]);
+            if (v[11]) atomicAdd(&d->nodes, v[11]);
+            if (v[12]) atomicAdd(&d->children, v[12]);
+            if (v[13]) atomicAdd(&d->hash_sum, v[13]);
+            if (hx) atomicXor(&d->hash_xor, hx);
+            if (om) atomicMax(&d->omega, om);
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kFoldRecs; k++) {
+            const uint32_t rk = (uint32_t)__shfl((int)res, (int)k, 64);
+            const unsigned long long ok = __shfl(hoff, (int)k, 64);
+            if (rk != kNoSlot && x[k] != 0ull) atomicAdd(&sp.hist[ok + lane], x[k]);
         }
     }
     if (mine != 0ull) {
