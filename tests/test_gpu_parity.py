@@ -393,6 +393,40 @@ def test_batch_matches_single(mce, orc):
     b.release()
 
 
+def test_exit_fold_totals_and_counters(mce, orc):
+    """The search's wavefronts leave their totals and counters in exit records
+    that a fold kernel adds up after the launch: on one graph (every record
+    reports to one result slot), on a batch (records of different slots, some
+    graphs shorter than a record's 64 histogram entries) and on a launch with
+    far more wavefronts than units (records that hold no graph), the results
+    equal the oracle's and the wall-clock shares add up to at most one."""
+    cases = [
+        ("one graph", [synth.gnp(300, 0.3, 5)], {}),
+        ("batch", [synth.gnp(n, p, s) for n, p, s in synth.batch_mix(24, 3)] + [synth.complete(4), synth.empty(3)], {}),
+        ("idle wavefronts", [synth.gnp(40, 0.5, 1)], {"blocks": 512, "waves_per_block": 8}),
+    ]
+    for name, graphs, opts in cases:
+        for k, v in opts.items():
+            mce.set_option(k, v)
+        try:
+            g = mce.Graph(batch=graphs) if len(graphs) > 1 else mce.Graph(graphs[0])
+            try:
+                out = g.count()
+                st = mce.last_stats()
+            finally:
+                g.release()
+        finally:
+            mce.reset_options(watchdog_ms=20000)
+        outs = out if isinstance(out, list) else [out]
+        assert len(outs) == len(graphs), name
+        for o, rows in zip(outs, graphs):
+            same(o, orc.greedy(rows))
+        assert st["units"] >= 1, name
+        assert 0.0 < st["busy_frac"] <= 1.0, name
+        assert st["ramp_frac"] >= 0.0 and st["tail_frac"] >= 0.0, name
+        assert st["busy_frac"] + st["ramp_frac"] + st["tail_frac"] <= 1.0 + 1e-9, name
+
+
 @pytest.mark.parametrize("opts", [
     {"lds_depth": 0},
     {"lds_depth": 1, "check_interval": 1, "split_threshold": 1 << 20},
