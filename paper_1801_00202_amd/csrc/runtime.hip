@@ -611,7 +611,7 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c, bool local = false)
     sp.refresh_children = o.refresh_children > 0 ? (uint32_t)o.refresh_children : sp.check_interval;
     if (sp.refresh_children < sp.check_interval) sp.refresh_children = sp.check_interval;
     // an idle workgroup reads the end-of-search counter every poll_iters looks
-    sp.poll_iters = 8;
+    sp.poll_iters = 4;
     return sp;
 }
 
