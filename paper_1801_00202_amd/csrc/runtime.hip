@@ -300,6 +300,7 @@ struct HostPinned {
         }
         return MCE_OK;
     }
+    template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
 uint32_t next_pow2(uint64_t x)
@@ -384,7 +385,9 @@ struct mce_graph_s {
     // bumped whenever a workspace buffer is reallocated: a captured graph holds
     // the buffer addresses of its capture and is replayed only while they stand
     uint64_t ws_gen = 0;
-    HostPinned h_out; // results | ctl | hist, copied back in one go
+    HostPinned h_out;  // results | ctl | hist, copied back in one go
+    HostPinned h_flag; // the validation verdict of rows given in device memory
+    HostPinned h_desc; // staging of d_desc's copy, kept while it may be in flight
     // chunk buffers of mce_enumerate_stream
     DevBuf d_sv, d_so;
     HostPinned h_sv, h_so;
@@ -410,7 +413,9 @@ struct mce_graph_s {
     int local_state = 0;
     uint32_t lcount = 0, lmax_w32 = 0, lmax_n = 0;
     DevBuf d_ldesc, d_ladj, d_lord, d_lidmap, d_lpx;
-    std::vector<GraphDesc> ldesc_host; // the source of d_ldesc's copy, kept while it may be in flight
+    // pinned host blocks of the build: the plan read back, and the layout
+    // (source of d_ldesc's copy, kept while it may be in flight)
+    HostPinned h_lplan, h_ldesc;
     hipEvent_t ev_local = nullptr;     // recorded after the local graphs' build
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float prepare_ms = 0.f;
@@ -723,19 +728,24 @@ int ensure_local(mce_graph_s* h, hipStream_t s)
     const uint32_t n = h->desc[0].n;
     DevBuf plan;
     int rc;
+    // pinned host memory on both copies: a pageable one is staged by the
+    // runtime and costs tens of microseconds more on every job
     if ((rc = plan.ensure(4ull * n)) != MCE_OK) return rc;
-    std::vector<uint32_t> hp(n);
+    if ((rc = h->h_lplan.ensure(4ull * n)) != MCE_OK) return rc;
+    if ((rc = h->h_ldesc.ensure(sizeof(GraphDesc) * n)) != MCE_OK) return rc;
+    const uint32_t* hp = h->h_lplan.as<uint32_t>();
+    GraphDesc* ld = h->h_ldesc.as<GraphDesc>();
     HIP_TRY(launch_local_plan(h->d_desc.as<GraphDesc>(), h->d_adj.as<uint32_t>(), n, plan.as<uint32_t>(), s));
-    HIP_TRY(hipMemcpyAsync(hp.data(), plan.p, 4ull * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->h_lplan.p, plan.p, 4ull * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    std::vector<GraphDesc> ld;
+    uint32_t count = 0;
     uint64_t adj = 0, ord = 0, px = 0;
     uint32_t mw = 0, mn = 0;
     for (uint32_t v = 0; v < n; v++) {
         if (!(hp[v] & 0x80000000u)) continue;
         const uint32_t k = (hp[v] & 0x7fffffffu) + 1u;
         if (k > kLocalMaxN) return MCE_OK; // a wide neighbourhood: the whole graph's layout instead
-        GraphDesc gd;
+        GraphDesc& gd = ld[count++];
         std::memset(&gd, 0, sizeof(gd));
         gd.n = k;
         gd.w32 = (k + 31u) / 32u;
@@ -752,25 +762,23 @@ int ensure_local(mce_graph_s* h, hipStream_t s)
         px += 2ull * gd.w32 + 1u;
         mw = std::max(mw, gd.w32);
         mn = std::max(mn, k);
-        ld.push_back(gd);
     }
-    if (ld.empty()) return MCE_OK;
-    if ((rc = h->d_ldesc.ensure(sizeof(GraphDesc) * ld.size())) != MCE_OK) return rc;
+    if (count == 0) return MCE_OK;
+    if ((rc = h->d_ldesc.ensure(sizeof(GraphDesc) * count)) != MCE_OK) return rc;
     // 128 words of padding: a row load reads up to 64 words from the row start
     if ((rc = h->d_ladj.ensure(4 * (adj + 128))) != MCE_OK) return rc;
     if ((rc = h->d_lord.ensure(4 * ord)) != MCE_OK) return rc;
     if ((rc = h->d_lidmap.ensure(4 * ord)) != MCE_OK) return rc;
     if ((rc = h->d_lpx.ensure(4 * px)) != MCE_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(h->d_ldesc.p, ld.data(), sizeof(GraphDesc) * ld.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_ldesc.p, ld, sizeof(GraphDesc) * count, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_local_build(h->d_desc.as<GraphDesc>(), h->d_adj.as<uint32_t>(), h->d_order.as<uint32_t>(), n,
-                               h->d_ldesc.as<GraphDesc>(), (uint32_t)ld.size(), h->d_ladj.as<uint32_t>(),
+                               h->d_ldesc.as<GraphDesc>(), count, h->d_ladj.as<uint32_t>(),
                                h->d_lord.as<uint32_t>(), h->d_lidmap.as<uint32_t>(), h->d_lpx.as<uint32_t>(), s));
     // no wait here: the build's end is an event that solves wait for (on
     // this stream, a no-op), and the host layout stays with the handle
     if (!h->ev_local) HIP_TRY(hipEventCreateWithFlags(&h->ev_local, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(h->ev_local, s));
-    h->lcount = (uint32_t)ld.size();
-    h->ldesc_host = std::move(ld);
+    h->lcount = count;
     h->lmax_w32 = mw;
     h->lmax_n = mn;
     h->local_state = 1;
@@ -1140,8 +1148,10 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
     if ((rc = h->d_adj.ensure(4 * (adj + 128))) != MCE_OK) return rc;
     if ((rc = h->d_order.ensure(4 * std::max<uint64_t>(ord, 1))) != MCE_OK) return rc;
     if ((rc = ensure_events(h.get())) != MCE_OK) return rc;
+    if ((rc = h->h_desc.ensure(sizeof(GraphDesc) * desc.size())) != MCE_OK) return rc;
+    std::memcpy(h->h_desc.p, desc.data(), sizeof(GraphDesc) * desc.size());
     HIP_TRY(hipEventRecord(h->ev[0], s));
-    HIP_TRY(hipMemcpyAsync(h->d_desc.p, desc.data(), sizeof(GraphDesc) * desc.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_desc.p, h->h_desc.p, sizeof(GraphDesc) * desc.size(), hipMemcpyHostToDevice, s));
     if (in_words)
         HIP_TRY(hipMemcpyAsync(h->d_in.p, rows, 8 * in_words,
                                dev_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
@@ -1152,10 +1162,10 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
         HIP_TRY(hipMemsetAsync(flag.p, 0, 4, s));
         for (const GraphDesc& gd : desc)
             if (gd.n) HIP_TRY(launch_validate(h->d_in.as<uint64_t>() + gd.in_off, gd.n, gd.rw64, flag.as<unsigned int>(), s));
-        unsigned int bad = 0;
-        HIP_TRY(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, s));
+        if ((rc = h->h_flag.ensure(4)) != MCE_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(h->h_flag.p, flag.p, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (bad) return MCE_E_INVAL;
+        if (*h->h_flag.as<unsigned int>()) return MCE_E_INVAL;
     }
     uint64_t max_words = 0;
     for (const GraphDesc& gd : desc) max_words = std::max<uint64_t>(max_words, (uint64_t)gd.n * gd.rw64);
