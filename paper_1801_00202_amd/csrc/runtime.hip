@@ -378,6 +378,9 @@ struct mce_graph_s {
     DevBuf d_desc, d_in, d_adj, d_order, d_nbr;
     // workspace of the solve
     DevBuf d_results, d_hist, d_ctl, d_rec, d_mail, d_mail_rec, d_spill, d_state, d_exit, d_params, d_sub;
+    // ctl | results | hist in one block, the layout of h_out, so that one copy
+    // brings them back (d_ctl, d_results and d_hist are views into it)
+    DevBuf d_out;
     HostPinned h_params; // staging of the search parameters of direct (not replayed) solves
     // parameter block of the captured graph: written once, before the capture,
     // and read by every replay; no other solve touches it
@@ -385,7 +388,7 @@ struct mce_graph_s {
     // bumped whenever a workspace buffer is reallocated: a captured graph holds
     // the buffer addresses of its capture and is replayed only while they stand
     uint64_t ws_gen = 0;
-    HostPinned h_out;  // results | ctl | hist, copied back in one go
+    HostPinned h_out;  // ctl | results | hist, copied back in one go
     HostPinned h_flag; // the validation verdict of rows given in device memory
     HostPinned h_desc; // staging of d_desc's copy, kept while it may be in flight
     // chunk buffers of mce_enumerate_stream
@@ -437,7 +440,7 @@ namespace {
 
 size_t out_bytes(const mce_graph_s* h)
 {
-    return sizeof(DevResult) * h->num_graphs + sizeof(QueueCtl) + 8 * h->hist_total;
+    return sizeof(QueueCtl) + sizeof(DevResult) * h->num_graphs + 8 * h->hist_total;
 }
 
 // Stack levels a spill chunk holds at first: enough for every search of
@@ -550,10 +553,10 @@ int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c);
 // the handle stale (see ws_gen).
 int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
 {
-    const void* before[] = {h->d_results.p, h->d_hist.p, h->d_ctl.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
+    const void* before[] = {h->d_out.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
                             h->d_spill.p, h->d_state.p, h->d_exit.p, h->h_out.p};
     const int rc = ensure_workspace_bufs(h, c);
-    const void* after[] = {h->d_results.p, h->d_hist.p, h->d_ctl.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
+    const void* after[] = {h->d_out.p, h->d_rec.p, h->d_mail.p, h->d_mail_rec.p,
                            h->d_spill.p, h->d_state.p, h->d_exit.p, h->h_out.p};
     if (std::memcmp(before, after, sizeof(before)) != 0) h->ws_gen++;
     return rc;
@@ -562,9 +565,13 @@ int ensure_workspace(mce_graph_s* h, const LaunchCfg& c)
 int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c)
 {
     int rc;
-    if ((rc = h->d_results.ensure(sizeof(DevResult) * h->num_graphs)) != MCE_OK) return rc;
-    if ((rc = h->d_hist.ensure(8 * std::max<uint64_t>(h->hist_total, 1))) != MCE_OK) return rc;
-    if ((rc = h->d_ctl.ensure(sizeof(QueueCtl))) != MCE_OK) return rc;
+    const size_t res_bytes = sizeof(DevResult) * h->num_graphs;
+    const size_t hist_bytes = 8 * std::max<uint64_t>(h->hist_total, 1);
+    if ((rc = h->d_out.ensure(sizeof(QueueCtl) + res_bytes + hist_bytes)) != MCE_OK) return rc;
+    char* o = h->d_out.as<char>();
+    h->d_ctl.borrow(o, sizeof(QueueCtl));
+    h->d_results.borrow(o + sizeof(QueueCtl), res_bytes);
+    h->d_hist.borrow(o + sizeof(QueueCtl) + res_bytes, hist_bytes);
     const uint64_t rec_words = kRecHeader + 4ull * c.w32cap;
     if ((rc = h->d_rec.ensure(4ull * rec_words * c.cap)) != MCE_OK) return rc;
     if ((rc = h->d_mail.ensure(sizeof(Mailbox) * (uint64_t)c.blocks)) != MCE_OK) return rc;
@@ -648,13 +655,8 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
     HIP_TRY(launch_search(sp, d_sp, local ? h->lmax_w32 : h->max_w32, c.blocks, c.wpb, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
     HIP_TRY(launch_exit_fold(sp, c.blocks * c.wpb, s));
-    char* out = static_cast<char*>(h->h_out.p);
-    HIP_TRY(hipMemcpyAsync(out, sp.results, sizeof(DevResult) * h->num_graphs, hipMemcpyDeviceToHost, s));
-    out += sizeof(DevResult) * h->num_graphs;
-    HIP_TRY(hipMemcpyAsync(out, sp.ctl, sizeof(QueueCtl), hipMemcpyDeviceToHost, s));
-    out += sizeof(QueueCtl);
-    if (h->hist_total)
-        HIP_TRY(hipMemcpyAsync(out, sp.hist, 8 * h->hist_total, hipMemcpyDeviceToHost, s));
+    // control block, results and histogram are one block (d_out), laid out as h_out
+    HIP_TRY(hipMemcpyAsync(h->h_out.p, sp.ctl, out_bytes(h), hipMemcpyDeviceToHost, s));
     return MCE_OK;
 }
 
@@ -696,9 +698,9 @@ void fill_empty_graph(uint64_t first, uint64_t last, mce_result_t* out)
 int read_results(mce_graph_s* h, uint64_t first, uint64_t last, mce_result_t* res, QueueCtl* ctl_out)
 {
     const char* out = static_cast<const char*>(h->h_out.p);
-    const DevResult* r = reinterpret_cast<const DevResult*>(out);
-    const QueueCtl* ctl = reinterpret_cast<const QueueCtl*>(out + sizeof(DevResult) * h->num_graphs);
-    const uint64_t* hist = reinterpret_cast<const uint64_t*>(out + sizeof(DevResult) * h->num_graphs + sizeof(QueueCtl));
+    const QueueCtl* ctl = reinterpret_cast<const QueueCtl*>(out);
+    const DevResult* r = reinterpret_cast<const DevResult*>(out + sizeof(QueueCtl));
+    const uint64_t* hist = reinterpret_cast<const uint64_t*>(out + sizeof(QueueCtl) + sizeof(DevResult) * h->num_graphs);
     if (ctl_out) *ctl_out = *ctl;
     for (uint32_t i = 0; i < h->num_graphs; i++) {
         if (h->desc[i].n == 0) fill_empty_graph(first, last, &res[i]);
@@ -1622,9 +1624,7 @@ int noalloc_setup(NoAllocCtx& x, int dev)
     take(h->d_desc, sizeof(GraphDesc));
     take(h->d_order, 4ull * MCE_NOALLOC_MAX_N);
     take(h->d_adj, 4ull * ((uint64_t)MCE_NOALLOC_MAX_N * (kNoAllocW32 + 1) + 128));
-    take(h->d_results, sizeof(DevResult));
-    take(h->d_hist, 8ull * (MCE_NOALLOC_MAX_N + 1));
-    take(h->d_ctl, sizeof(QueueCtl));
+    take(h->d_out, sizeof(QueueCtl) + sizeof(DevResult) + 8ull * (MCE_NOALLOC_MAX_N + 1));
     take(h->d_params, sizeof(SearchParams));
     take(h->d_sub, 256); // the validation flag
     take(h->d_rec, rec_bytes * kNoAllocRecords);
