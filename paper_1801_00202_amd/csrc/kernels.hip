@@ -932,10 +932,17 @@ __global__ void __launch_bounds__(256) relabel_kernel(const GraphDesc* graphs, c
 
 // Zero the per-graph results, the histograms, the control block and the
 // mailboxes.
-__global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist_total, uint32_t workgroups)
+static_assert(sizeof(SearchParams) % 4 == 0 && sizeof(SearchParams) <= 4 * 256,
+              "SearchParams copied as words by the first workgroup of 256 threads");
+__global__ void reset_kernel(SearchParams sp, uint32_t num_graphs, uint64_t hist_total, uint32_t workgroups,
+                             SearchParams* params_out)
 {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // the search's copy of its parameters in HBM (read by the out-of-line
+    // helpers), written from this launch's own argument: no host copy
+    if (params_out && tid < sizeof(SearchParams) / 4)
+        reinterpret_cast<uint32_t*>(params_out)[tid] = reinterpret_cast<const uint32_t*>(&sp)[tid];
     unsigned long long* res = reinterpret_cast<unsigned long long*>(sp.results);
     const uint64_t res_words = (uint64_t)num_graphs * (sizeof(DevResult) / 8);
     for (uint64_t i = tid; i < res_words; i += stride) res[i] = 0ull;
@@ -3201,7 +3208,7 @@ hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t
 }
 
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
-                        uint32_t workgroups, hipStream_t s)
+                        uint32_t workgroups, SearchParams* params_out, hipStream_t s)
 {
     (void)hipGetLastError(); // report only this call's launch errors
     uint64_t work = hist_total;
@@ -3210,7 +3217,8 @@ hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hi
     uint32_t blocks = (uint32_t)((work + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, sp, num_graphs, hist_total, workgroups);
+    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, sp, num_graphs, hist_total, workgroups,
+                       params_out);
     return hipGetLastError();
 }
 

@@ -212,8 +212,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t value, hipStrea
 hipError_t launch_relabel(const GraphDesc* graphs, uint32_t num_graphs, uint32_t max_n,
                           const uint64_t* rows_in, const uint32_t* order, uint32_t* adj,
                           hipStream_t s);
+// Zeroes the results, histogram, mailboxes and control block of a solve, and
+// writes sp to params_out when that is not null.
 hipError_t launch_reset(const SearchParams& sp, uint32_t num_graphs, uint64_t hist_total,
-                        uint32_t workgroups, hipStream_t s);
+                        uint32_t workgroups, SearchParams* params_out, hipStream_t s);
 hipError_t launch_root(const SearchParams& sp, uint32_t num_graphs, uint32_t max_w32,
                        uint64_t first, uint64_t last, uint32_t max_units, hipStream_t s);
 hipError_t launch_subproblem(const SearchParams& sp, uint32_t max_w32, const uint32_t* bits, hipStream_t s);

@@ -381,7 +381,6 @@ struct mce_graph_s {
     // ctl | results | hist in one block, the layout of h_out, so that one copy
     // brings them back (d_ctl, d_results and d_hist are views into it)
     DevBuf d_out;
-    HostPinned h_params; // staging of the search parameters of direct (not replayed) solves
     // parameter block of the captured graph: written once, before the capture,
     // and read by every replay; no other solve touches it
     DevBuf d_params_graph;
@@ -581,7 +580,6 @@ int ensure_workspace_bufs(mce_graph_s* h, const LaunchCfg& c)
     if ((rc = h->d_state.ensure(4ull * c.blocks * c.wpb)) != MCE_OK) return rc;
     if ((rc = h->d_exit.ensure(sizeof(WaveExit) * c.blocks * c.wpb)) != MCE_OK) return rc;
     if ((rc = h->d_params.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
-    if ((rc = h->h_params.ensure(sizeof(SearchParams))) != MCE_OK) return rc;
     if ((rc = h->h_out.ensure(out_bytes(h))) != MCE_OK) return rc;
     return MCE_OK;
 }
@@ -629,12 +627,13 @@ SearchParams make_params(mce_graph_s* h, const LaunchCfg& c, bool local = false)
 
 // The solve sequence on a stream: reset, root, search, copy-out.
 // d_sp: device copy of sp already written by the caller (a graph capture), or
-// null to stage sp through the handle's pinned block into d_params.
+// null: the reset kernel writes sp (its own argument) into d_params.
 int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, uint64_t first,
                   uint64_t last, hipStream_t s, bool timed, const uint32_t* sub_bits = nullptr,
                   const SearchParams* d_sp = nullptr, bool local = false)
 {
-    HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.blocks, s));
+    HIP_TRY(launch_reset(sp, h->num_graphs, h->hist_total, c.blocks, d_sp ? nullptr : h->d_params.as<SearchParams>(),
+                         s));
     if (local) {
         // the root children [first, last) of the local graphs
         HIP_TRY(launch_local_units(sp, h->d_lpx.as<uint32_t>(), h->lcount, h->lmax_w32, first, last, s));
@@ -646,11 +645,7 @@ int enqueue_solve(mce_graph_s* h, const LaunchCfg& c, const SearchParams& sp, ui
         const uint32_t max_units = std::max<uint32_t>(1u, c.cap / h->num_graphs);
         HIP_TRY(launch_root(sp, h->num_graphs, h->max_w32, first, last, max_units, s));
     }
-    if (!d_sp) {
-        std::memcpy(h->h_params.p, &sp, sizeof(sp));
-        HIP_TRY(hipMemcpyAsync(h->d_params.p, h->h_params.p, sizeof(sp), hipMemcpyHostToDevice, s));
-        d_sp = h->d_params.as<SearchParams>();
-    }
+    if (!d_sp) d_sp = h->d_params.as<SearchParams>();
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
     HIP_TRY(launch_search(sp, d_sp, local ? h->lmax_w32 : h->max_w32, c.blocks, c.wpb, s));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], s));
@@ -1592,7 +1587,7 @@ struct NoAllocCtx {
     bool ready = false;
     char* base = nullptr;          // device address of this device's scratch
     mce_graph_s* h = nullptr;      // a handle whose buffers are views of the scratch
-    std::vector<unsigned char> host_out, host_params; // fixed host blocks
+    std::vector<unsigned char> host_out; // fixed host block
 };
 
 NoAllocCtx g_noalloc[kNoAllocDevices];
@@ -1635,9 +1630,7 @@ int noalloc_setup(NoAllocCtx& x, int dev)
     if (off >= MCE_NOALLOC_SCRATCH_BYTES) return MCE_E_NOMEM;
     h->d_spill.borrow(x.base + off, MCE_NOALLOC_SCRATCH_BYTES - off);
     x.host_out.assign(sizeof(DevResult) + sizeof(QueueCtl) + 8ull * (MCE_NOALLOC_MAX_N + 1), 0);
-    x.host_params.assign(sizeof(SearchParams), 0);
     h->h_out.borrow(x.host_out.data(), x.host_out.size());
-    h->h_params.borrow(x.host_params.data(), x.host_params.size());
     int rc = ensure_events(h.get());
     if (rc != MCE_OK) return rc;
     x.h = h.release();
