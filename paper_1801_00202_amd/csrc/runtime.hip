@@ -388,7 +388,7 @@ struct mce_graph_s {
     // the buffer addresses of its capture and is replayed only while they stand
     uint64_t ws_gen = 0;
     HostPinned h_out;  // ctl | results | hist, copied back in one go
-    HostPinned h_flag; // the validation verdict of rows given in device memory
+    HostPinned h_flag; // the validation flag of rows given in device memory, read back
     HostPinned h_desc; // staging of d_desc's copy, kept while it may be in flight
     // chunk buffers of mce_enumerate_stream
     DevBuf d_sv, d_so;
@@ -1153,7 +1153,7 @@ int mce_prepare(uint32_t n, const uint64_t* rows, uint32_t row_words, const mce_
         HIP_TRY(hipMemcpyAsync(h->d_in.p, rows, 8 * in_words,
                                dev_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     if (dev_ptr) {
-        // validate on the device, then wait for the verdict
+        // validate on the device, then wait for the flag
         DevBuf flag;
         if ((rc = flag.ensure(4)) != MCE_OK) return rc;
         HIP_TRY(hipMemsetAsync(flag.p, 0, 4, s));
